@@ -1,0 +1,195 @@
+/*
+ * sdpd.h -- C ABI of libsdpd, Smoothed Dissipative Particle Dynamics with the
+ * Metropolized fluctuation/dissipation scheme of Faure & Stoltz, "Stable and
+ * accurate schemes for Smoothed Dissipative Particle Dynamics"
+ * (arXiv:1707.04232), on AMD Instinct MI355X (gfx950).
+ *
+ * Conventions
+ *  - All floating point is IEEE binary64.
+ *  - State arrays are DEVICE pointers owned by the caller, structure of
+ *    arrays: a 3-vector field of n particles is 3*n doubles, x[0..n) then
+ *    y[0..n) then z[0..n).  Every array must be 8-byte aligned and hold n
+ *    (or 3n) elements.  The library never frees them.
+ *  - A context owns all workspace (cell lists, pair masks, partial sums,
+ *    counters, the sticky device error word), sized at sdpd_create for n.
+ *  - Calls are asynchronous on the stream given at sdpd_create unless they
+ *    return statistics (then they synchronise that stream).  One context must
+ *    not be used from two host threads at once.
+ *  - Every call returns an sdpd_status.  Argument errors are detected on the
+ *    host before any launch and leave the state unchanged.  Conditions found
+ *    on the device (cell overflow, negative energy in SSA mode, non-finite
+ *    values) set a sticky error word that the next synchronising call
+ *    returns; after such an error the state is unspecified.
+ */
+#ifndef SDPD_H
+#define SDPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDPD_ABI_VERSION 1
+
+typedef enum {
+    SDPD_OK = 0,
+    SDPD_EINVAL = -1,     /* bad argument or parameter (host check)          */
+    SDPD_EHIP = -2,       /* a HIP runtime call failed                        */
+    SDPD_ENOMEM = -3,     /* workspace allocation failed                      */
+    SDPD_ECELLCAP = -4,   /* a cell holds more than cell_cap particles        */
+    SDPD_ENEGEPS = -5,    /* SSA mode produced eps <= 0 (Sec. 3.2 of the paper) */
+    SDPD_ENONFINITE = -6  /* a position, energy or density is not finite      */
+} sdpd_status;
+
+/* SPH kernel W with support h (Sec. 2.1.1): Lucy's quartic, or the paper's
+ * cubic spline of eq. (sdpd-cubic-w).                                       */
+typedef enum { SDPD_KERNEL_LUCY = 0, SDPD_KERNEL_CUBIC = 1 } sdpd_kernel;
+
+/* fluctuation/dissipation scheme: exact Metropolis (EMS, Sec. 3.3.2),
+ * approximate Metropolis rejecting only negative energies (AMS, Sec. 3.3.3),
+ * the Shardlow-like splitting without rejection (SSA, Sec. 3.2), or none.  */
+typedef enum { SDPD_FD_EMS = 0, SDPD_FD_AMS = 1, SDPD_FD_SSA = 2, SDPD_FD_NONE = 3 } sdpd_fd;
+
+typedef enum { SDPD_FP64 = 0 } sdpd_prec;
+
+/* Physical and numerical parameters.  Ideal-gas entropy closure
+ *   S(eps, rho) = Cv ln eps - A kB ln(rho / rho0)          (eq. pg-eos)
+ * so T = eps/Cv, P = A kB rho eps / (m Cv), C = Cv (Sec. 2.1.2).
+ * Requirements: n >= 0; m, h, kB, Cv, A, rho0, dt > 0; Cv > kB/2 (so that
+ * d_ij < 1); eta > 0 and 0 <= zeta < 5 eta / 3 (both kappas positive);
+ * box[k] / ncell[k] >= h with ncell[k] even and >= 4 (ncell[k] = 0 picks the
+ * largest even integer <= box[k]/h); 1 <= cell_cap <= 64; fd_every >= 1.   */
+typedef struct {
+    int64_t n;            /* number of particles                            */
+    double box[3];        /* periodic box lengths                           */
+    double m, h, kB;      /* particle mass, smoothing length, Boltzmann     */
+    double Cv, A, rho0;   /* heat capacity, EOS density exponent, ref. density */
+    double eta, zeta;     /* shear and bulk viscosity                       */
+    double dt;            /* time step                                      */
+    int32_t fd_every;     /* theta: F/D every theta steps with theta*dt (Sec. 4.2) */
+    int32_t kernel;       /* sdpd_kernel                                    */
+    int32_t fd;           /* sdpd_fd                                        */
+    int32_t prec;         /* sdpd_prec                                      */
+    uint64_t seed;        /* Philox key                                     */
+    uint32_t replica;     /* replica index, part of the Philox counter      */
+    int32_t cell_cap;     /* max particles per cell (<= 64)                 */
+    int32_t ncell[3];     /* cells per axis, 0 = automatic                  */
+} sdpd_params;
+
+/* Particle state, device pointers (see Conventions).  eps > 0.            */
+typedef struct {
+    double *q;            /* positions in [0, box), 3n                      */
+    double *p;            /* momenta, 3n                                    */
+    double *eps;          /* internal energies, n                           */
+    double *rho;          /* densities, n                                   */
+    double *f;            /* conservative forces, 3n                        */
+    uint32_t *id;         /* particle identities (distinct), n              */
+} sdpd_state;
+
+/* Counters of one F/D sweep and observables after a step.                */
+typedef struct {
+    uint64_t proposed;    /* active pairs visited                           */
+    uint64_t rej_energy;  /* rejected by the energy bound, eq. (energy-bound) */
+    uint64_t rej_ratio;   /* rejected by the Metropolis test                */
+    uint64_t marginal;    /* decisions within the rounding margin           */
+    uint64_t negeps;      /* SSA moves that made an energy non-positive     */
+    double E, Eint, KE;   /* total, internal and kinetic energy (Sec. 2.2.1) */
+    double P[3];          /* total momentum                                 */
+    double min_eps;       /* smallest internal energy                       */
+} sdpd_stats;
+
+typedef struct sdpd_ctx sdpd_ctx;
+
+/* Create a context for params->n particles on the current HIP device.
+ * hip_stream: a hipStream_t (NULL = the default stream) that every later
+ * call of this context launches on.  *out receives the context.
+ * Errors: SDPD_EINVAL (parameters), SDPD_ENOMEM, SDPD_EHIP.                */
+int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out);
+
+/* Destroy a context (synchronises its stream, frees its workspace).       */
+int sdpd_destroy(sdpd_ctx *ctx);
+
+/* Cell list (not part of the paper; it defines the pair schedule, see
+ * sdpd_fd_metropolis).  Sorts the state in place by (cell, id): cell c =
+ * cx + nx (cy + ny cz) with ck = floor(q_k * ncell_k / box_k) clamped to
+ * [0, ncell_k); within a cell by increasing id (the slot).  All six arrays
+ * are permuted; cell_start[0..ncell] is kept in the context.  A cell with
+ * more than cell_cap particles raises SDPD_ECELLCAP (sticky).             */
+int sdpd_build_cells(sdpd_ctx *ctx, const sdpd_state *state);
+
+/* Device pointer to the context's cell_start array (ncell+1 uint32) and
+ * the cell counts per axis (for inspection; valid until the next call).   */
+int sdpd_cell_info(sdpd_ctx *ctx, int32_t ncell[3], const uint32_t **cell_start);
+
+/* Copy cell_start (ncell+1 uint32) into the HOST array dst of capacity
+ * entries (sync).  SDPD_EINVAL if capacity < ncell + 1.                   */
+int sdpd_copy_cell_start(sdpd_ctx *ctx, uint32_t *dst, int64_t capacity);
+
+/* SPH density, eq. (sdpd-rho-v): rho_i = sum_j m W(r_ij) over all j with
+ * r_ij < h (minimum image) including j = i.  Requires the state to be in
+ * the order of the last sdpd_build_cells.  If update_eps_const_S != 0 the
+ * internal energies follow the entropy-conserving update of Sec. 3.1:
+ * eps_i <- eps_i (rho_new_i / rho_old_i)^(A kB / Cv), rho_old being the
+ * rho array on entry.  Also records the active-pair masks that
+ * sdpd_fd_metropolis uses.                                                 */
+int sdpd_density(sdpd_ctx *ctx, const sdpd_state *state, int update_eps_const_S);
+
+/* Conservative forces, eq. (cons-forces):
+ *   f_i = sum_{j != i, r_ij < h} m^2 (P_i/rho_i^2 + P_j/rho_j^2) F_ij r_ij
+ * with P from the closure at (eps, rho).  Requires the cell order.        */
+int sdpd_forces(sdpd_ctx *ctx, const sdpd_state *state);
+
+/* One fluctuation/dissipation sweep with time step fd_every * dt: every
+ * pair with r_ij < h is updated once, EMS/AMS/SSA per params->fd (Sec. 3.2,
+ * 3.3), with i the smaller id.  Pair (i, j) draws its Gaussian vector and
+ * uniform from Philox4x32-10 with key seed and counter
+ * (step, id_i, id_j, 2 replica + k), k = 0, 1.  Pairs are applied in
+ * ascending (phase, round): phase 0 = pairs inside a cell, phase
+ * 1 + 8 o + pi = pairs between cell A of coordinate parity pi and its o-th
+ * forward neighbour (o = 0..12, the offsets after the centre of the
+ * z-slowest 27-list); round = slot_A XOR slot_B.  Equal keys share no
+ * particle.  Requires sdpd_density on the current cell order (for the pair
+ * masks and rho).  If out is not NULL the counters are returned (sync).    */
+int sdpd_fd_metropolis(sdpd_ctx *ctx, const sdpd_state *state, uint64_t step,
+                       sdpd_stats *out);
+
+/* nsteps full steps, step indices step0 .. step0+nsteps-1, each:
+ *   p += dt/2 f; q += dt p/m (wrapped once into [0, box)); build cells;
+ *   density with the entropy-conserving energy update; if step % fd_every
+ *   == 0 an F/D sweep; forces; p += dt/2 f     (eq. sdpd-verlet + splitting)
+ * On entry rho and f must belong to q (sdpd_build_cells, sdpd_density(0),
+ * sdpd_forces).  per_step (host array of nsteps, or NULL) receives each
+ * step's counters and observables; it makes the call synchronise once at
+ * the end.  Without it the call is asynchronous.                          */
+int sdpd_step(sdpd_ctx *ctx, const sdpd_state *state, uint64_t step0, int nsteps,
+              sdpd_stats *per_step);
+
+/* Observables of the current state (sync): E, Eint, KE, P, min_eps.       */
+int sdpd_observe(sdpd_ctx *ctx, const sdpd_state *state, sdpd_stats *out);
+
+/* Wait for the context's stream and return (then clear) the first sticky
+ * device error, or SDPD_OK.                                               */
+int sdpd_sync(sdpd_ctx *ctx);
+
+/* Kernel timing with HIP events on the context's stream.  sdpd_set_timing
+ * (sync) switches it on or off and clears the record; while on, every launch
+ * of the classes below is bracketed by two events.  sdpd_timing (sync)
+ * returns, per class, the summed milliseconds and the number of launches
+ * since the last call, then clears the record.  Classes: 0 cell build,
+ * 1 density, 2 F/D phase kernels, 3 forces + half kick, 4 observables.     */
+int sdpd_set_timing(sdpd_ctx *ctx, int enable);
+int sdpd_timing(sdpd_ctx *ctx, double ms[5], int64_t launches[5]);
+
+/* Execution-only tuning of the F/D sweep (results do not change): tasks
+ * (cells, resp. cell pairs) given to one workgroup in phase 0 and in the
+ * inter-cell phases.  Both >= 1.                                          */
+int sdpd_tune(sdpd_ctx *ctx, int fd_tasks_intra, int fd_tasks_inter);
+
+const char *sdpd_strerror(int status);
+int sdpd_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

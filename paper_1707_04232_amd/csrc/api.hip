@@ -1,0 +1,427 @@
+// C ABI of libsdpd: parameter checks, workspace, launch order, errors.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "sdpd_internal.hpp"
+
+namespace sdpd {
+
+int check_hip(hipError_t e) { return e == hipSuccess ? SDPD_OK : SDPD_EHIP; }
+
+void timer_begin(sdpd_ctx *c, int k)
+{
+    if (!c->timing) return;
+    Timer &T = c->timer;
+    if (T.used + 2 > T.pool.size()) {
+        size_t old = T.pool.size();
+        T.pool.resize(old + 4096);
+        for (size_t i = old; i < T.pool.size(); ++i) (void)hipEventCreate(&T.pool[i]);
+        T.cls.resize(T.pool.size() / 2);
+    }
+    T.cls[T.used / 2] = k;
+    (void)hipEventRecord(T.pool[T.used], c->stream);
+}
+
+void timer_end(sdpd_ctx *c, int k)
+{
+    (void)k;
+    if (!c->timing) return;
+    Timer &T = c->timer;
+    (void)hipEventRecord(T.pool[T.used + 1], c->stream);
+    T.used += 2;
+}
+
+static bool valid_positive(double x) { return isfinite(x) && x > 0.0; }
+
+// number of cells per axis (the requested value or the largest even
+// integer <= box/h), or -1 when the grid would not cover the cutoff
+static int grid_axis(double box, double h, int req)
+{
+    int c = req;
+    if (c <= 0) {
+        c = (int)floor(box / h);
+        if (c % 2) c -= 1;
+    }
+    if (c < 4 || c % 2 || box / c < h) return -1;
+    return c;
+}
+
+static int check_params(const sdpd_params *P, int nc[3])
+{
+    if (!P) return SDPD_EINVAL;
+    if (P->n < 0 || P->n > 0x7fffffffLL) return SDPD_EINVAL;
+    if (!valid_positive(P->m) || !valid_positive(P->h) || !valid_positive(P->kB) ||
+        !valid_positive(P->Cv) || !valid_positive(P->A) || !valid_positive(P->rho0) ||
+        !valid_positive(P->dt) || !valid_positive(P->eta))
+        return SDPD_EINVAL;
+    if (!(P->Cv > 0.5 * P->kB)) return SDPD_EINVAL;           // d_ij < 1
+    if (!(isfinite(P->zeta) && P->zeta >= 0.0 && P->zeta < 5.0 * P->eta / 3.0))
+        return SDPD_EINVAL;                                   // kappa_perp > 0
+    if (P->kernel != SDPD_KERNEL_LUCY && P->kernel != SDPD_KERNEL_CUBIC) return SDPD_EINVAL;
+    if (P->fd < SDPD_FD_EMS || P->fd > SDPD_FD_NONE) return SDPD_EINVAL;
+    if (P->prec != SDPD_FP64) return SDPD_EINVAL;
+    if (P->cell_cap < 1 || P->cell_cap > MAX_CAP) return SDPD_EINVAL;
+    if (P->fd_every < 1) return SDPD_EINVAL;
+    int64_t ncell = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (!valid_positive(P->box[k])) return SDPD_EINVAL;
+        nc[k] = grid_axis(P->box[k], P->h, P->ncell[k]);
+        if (nc[k] < 0) return SDPD_EINVAL;
+        ncell *= nc[k];
+    }
+    if (ncell >= 0xffffffffLL) return SDPD_EINVAL;
+    return SDPD_OK;
+}
+
+static void derive(const sdpd_params *P, const int nc[3], DevParams &d)
+{
+    const double pi = 3.14159265358979323846;
+    memset(&d, 0, sizeof d);
+    d.n = P->n;
+    d.ncell = 1;
+    for (int k = 0; k < 3; ++k) {
+        d.box[k] = P->box[k];
+        d.half_box[k] = 0.5 * P->box[k];
+        d.nc[k] = nc[k];
+        d.inv_cell[k] = (double)nc[k] / P->box[k];
+        d.ncell *= nc[k];
+    }
+    d.m = P->m;
+    d.inv_m = 1.0 / P->m;
+    d.h = P->h;
+    d.h2 = P->h * P->h;
+    d.inv_h = 1.0 / P->h;
+    d.kB = P->kB;
+    d.Cv = P->Cv;
+    d.inv_Cv = 1.0 / P->Cv;
+    d.A = P->A;
+    d.dt = P->dt;
+    d.kernel = P->kernel;
+    d.fd = P->fd;
+    d.cap = P->cell_cap;
+    d.seed_lo = (uint32_t)P->seed;
+    d.seed_hi = (uint32_t)(P->seed >> 32);
+    d.replica = P->replica;
+    const double h = P->h;
+    if (P->kernel == SDPD_KERNEL_LUCY) {
+        d.cW = 105.0 / (16.0 * pi * h * h * h);
+        d.cF = 315.0 / (4.0 * pi * pow(h, 5));
+    } else {
+        d.cW = 8.0 / (pi * h * h * h);
+        d.cF = 48.0 / (pi * pow(h, 5));
+    }
+    d.cPi = P->A * P->kB / (P->m * P->Cv);
+    d.eps_exp = P->A * P->kB / P->Cv;
+    d.kpar_c = (10.0 / 3.0 * P->eta + 4.0 * P->zeta) * P->m * P->m;
+    d.kperp_c = (5.0 / 3.0 * P->eta - P->zeta) * P->m * P->m;
+    d.two_over_Cv = 2.0 / P->Cv;
+    d.b2_c = 4.0 * P->kB / P->m;
+    d.ent_c = P->Cv / P->kB - 1.0;
+    d.m_over_8 = P->m / 8.0;
+    d.m_over_2 = P->m / 2.0;
+}
+
+template <typename T>
+static int dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, sizeof(T) * count) == hipSuccess ? SDPD_OK : SDPD_ENOMEM;
+}
+
+static void free_ctx(sdpd_ctx *c)
+{
+    void *bufs[] = {c->cell_of, c->count, c->cursor, c->cell_start, c->block_sums, c->tmp_idx,
+                    c->perm, c->cell_sorted, c->tq, c->tp, c->teps, c->trho, c->tf, c->tid,
+                    c->pi, c->masks, c->counters, c->err, c->obs_partial, c->obs_out};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+static bool state_ok(const sdpd_ctx *c, const sdpd_state *s)
+{
+    if (!s) return false;
+    if (c->n == 0) return true;
+    return s->q && s->p && s->eps && s->rho && s->f && s->id;
+}
+
+static int take_error(sdpd_ctx *c)
+{
+    uint32_t e = 0;
+    if (hipMemcpyAsync(&e, c->err, sizeof e, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return SDPD_EHIP;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return SDPD_EHIP;
+    if (e) {
+        uint32_t z = 0;
+        if (hipMemcpy(c->err, &z, sizeof z, hipMemcpyHostToDevice) != hipSuccess) return SDPD_EHIP;
+    }
+    if (e & ERR_CELLCAP) return SDPD_ECELLCAP;
+    if (e & ERR_NONFINITE) return SDPD_ENONFINITE;
+    if (e & ERR_NEGEPS) return SDPD_ENEGEPS;
+    return SDPD_OK;
+}
+
+static void record_to_stats(const double *rec, sdpd_stats *st)
+{
+    st->E = rec[0];
+    st->Eint = rec[1];
+    st->KE = rec[2];
+    st->P[0] = rec[3];
+    st->P[1] = rec[4];
+    st->P[2] = rec[5];
+    st->min_eps = rec[6];
+    uint64_t cnt[CNT_N];
+    memcpy(cnt, rec + 7, sizeof cnt);
+    st->proposed = cnt[CNT_PROPOSED];
+    st->rej_energy = cnt[CNT_REJ_ENERGY];
+    st->rej_ratio = cnt[CNT_REJ_RATIO];
+    st->marginal = cnt[CNT_MARGINAL];
+    st->negeps = cnt[CNT_NEGEPS];
+}
+
+static int ensure_records(sdpd_ctx *c, int64_t count)
+{
+    if (count <= c->obs_cap) return SDPD_OK;
+    if (c->obs_out) (void)hipFree(c->obs_out);
+    c->obs_out = nullptr;
+    c->obs_cap = 0;
+    int rc = dalloc(&c->obs_out, (size_t)(count * REC));
+    if (!rc) c->obs_cap = count;
+    return rc;
+}
+
+}  // namespace sdpd
+
+using namespace sdpd;
+
+extern "C" {
+
+int sdpd_abi_version(void) { return SDPD_ABI_VERSION; }
+
+const char *sdpd_strerror(int s)
+{
+    switch (s) {
+    case SDPD_OK: return "success";
+    case SDPD_EINVAL: return "invalid argument or parameter";
+    case SDPD_EHIP: return "HIP runtime error";
+    case SDPD_ENOMEM: return "out of device memory";
+    case SDPD_ECELLCAP: return "a cell holds more particles than cell_cap";
+    case SDPD_ENEGEPS: return "non-positive internal energy (SSA)";
+    case SDPD_ENONFINITE: return "non-finite or non-positive state value";
+    default: return "unknown status";
+    }
+}
+
+int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
+{
+    if (!out) return SDPD_EINVAL;
+    *out = nullptr;
+    int nc[3];
+    int rc = check_params(params, nc);
+    if (rc) return rc;
+    sdpd_ctx *c = new (std::nothrow) sdpd_ctx();
+    if (!c) return SDPD_ENOMEM;
+    c->prm = *params;
+    derive(params, nc, c->dp);
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return SDPD_EHIP;
+    }
+    c->n = params->n;
+    c->ncell = c->dp.ncell;
+    const size_t n = (size_t)c->n, nce = (size_t)c->ncell;
+    c->nscan_blocks = (int64_t)((nce + 1023) / 1024);
+    c->obs_blocks = c->n > 0 ? std::min<int64_t>(1024, (c->n + 255) / 256) : 1;
+    c->fd_tasks_intra = 16;
+    c->fd_tasks_inter = 8;
+    rc = SDPD_OK;
+    rc = rc ? rc : dalloc(&c->cell_of, n);
+    rc = rc ? rc : dalloc(&c->count, nce);
+    rc = rc ? rc : dalloc(&c->cursor, nce);
+    rc = rc ? rc : dalloc(&c->cell_start, nce + 1);
+    rc = rc ? rc : dalloc(&c->block_sums, (size_t)c->nscan_blocks);
+    rc = rc ? rc : dalloc(&c->tmp_idx, n);
+    rc = rc ? rc : dalloc(&c->perm, n);
+    rc = rc ? rc : dalloc(&c->cell_sorted, n);
+    rc = rc ? rc : dalloc(&c->tq, 3 * n);
+    rc = rc ? rc : dalloc(&c->tp, 3 * n);
+    rc = rc ? rc : dalloc(&c->tf, 3 * n);
+    rc = rc ? rc : dalloc(&c->teps, n);
+    rc = rc ? rc : dalloc(&c->trho, n);
+    rc = rc ? rc : dalloc(&c->tid, n);
+    rc = rc ? rc : dalloc(&c->pi, n);
+    rc = rc ? rc : dalloc(&c->masks, (size_t)NMASK * n);
+    rc = rc ? rc : dalloc(&c->counters, (size_t)CNT_N);
+    rc = rc ? rc : dalloc(&c->err, 1);
+    rc = rc ? rc : dalloc(&c->obs_partial, (size_t)c->obs_blocks * 6);
+    rc = rc ? rc : ensure_records(c, 64);
+    if (!rc) rc = launch_fill_u32(c, c->err, 0u, 1);
+    if (!rc) rc = launch_fill_u64(c, c->counters, 0ull, CNT_N);
+    if (!rc) rc = check_hip(hipStreamSynchronize(c->stream));
+    if (rc) {
+        free_ctx(c);
+        return rc;
+    }
+    *out = c;
+    return SDPD_OK;
+}
+
+int sdpd_destroy(sdpd_ctx *c)
+{
+    if (!c) return SDPD_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    free_ctx(c);
+    return SDPD_OK;
+}
+
+int sdpd_build_cells(sdpd_ctx *c, const sdpd_state *s)
+{
+    if (!c || !state_ok(c, s)) return SDPD_EINVAL;
+    return run_build_cells(c, s, 0);
+}
+
+int sdpd_cell_info(sdpd_ctx *c, int32_t ncell[3], const uint32_t **cell_start)
+{
+    if (!c || !ncell || !cell_start) return SDPD_EINVAL;
+    for (int k = 0; k < 3; ++k) ncell[k] = c->dp.nc[k];
+    *cell_start = c->cell_start;
+    return SDPD_OK;
+}
+
+int sdpd_copy_cell_start(sdpd_ctx *c, uint32_t *dst, int64_t capacity)
+{
+    if (!c || !dst || capacity < c->ncell + 1) return SDPD_EINVAL;
+    int rc = check_hip(hipMemcpyAsync(dst, c->cell_start, sizeof(uint32_t) * (size_t)(c->ncell + 1),
+                                      hipMemcpyDeviceToHost, c->stream));
+    if (rc) return rc;
+    return check_hip(hipStreamSynchronize(c->stream));
+}
+
+int sdpd_density(sdpd_ctx *c, const sdpd_state *s, int update_eps_const_S)
+{
+    if (!c || !state_ok(c, s) || !c->cells_valid) return SDPD_EINVAL;
+    return run_density(c, s, update_eps_const_S != 0);
+}
+
+int sdpd_forces(sdpd_ctx *c, const sdpd_state *s)
+{
+    if (!c || !state_ok(c, s) || !c->cells_valid) return SDPD_EINVAL;
+    return run_forces(c, s, 0);
+}
+
+int sdpd_fd_metropolis(sdpd_ctx *c, const sdpd_state *s, uint64_t step, sdpd_stats *out)
+{
+    if (!c || !state_ok(c, s) || !c->cells_valid || !c->masks_valid) return SDPD_EINVAL;
+    int rc = launch_fill_u64(c, c->counters, 0ull, CNT_N);
+    if (!rc) rc = run_fd_sweep(c, s, step, c->prm.dt * c->prm.fd_every);
+    if (rc) return rc;
+    if (out) {
+        if ((rc = run_observe(c, s, c->obs_out))) return rc;
+        double rec[REC];
+        if ((rc = check_hip(hipMemcpyAsync(rec, c->obs_out, sizeof rec, hipMemcpyDeviceToHost,
+                                           c->stream))))
+            return rc;
+        rc = take_error(c);
+        record_to_stats(rec, out);
+        return rc;
+    }
+    return SDPD_OK;
+}
+
+int sdpd_step(sdpd_ctx *c, const sdpd_state *s, uint64_t step0, int nsteps, sdpd_stats *per_step)
+{
+    if (!c || !state_ok(c, s) || nsteps < 0 || !c->cells_valid) return SDPD_EINVAL;
+    int rc;
+    if (per_step && (rc = ensure_records(c, nsteps))) return rc;
+    const uint64_t theta = (uint64_t)c->prm.fd_every;
+    for (int k = 0; k < nsteps; ++k) {
+        const uint64_t step = step0 + (uint64_t)k;
+        if ((rc = run_build_cells(c, s, 1))) return rc;
+        if ((rc = run_density(c, s, 1))) return rc;
+        if ((rc = launch_fill_u64(c, c->counters, 0ull, CNT_N))) return rc;
+        if (step % theta == 0 && (rc = run_fd_sweep(c, s, step, c->prm.dt * (double)theta)))
+            return rc;
+        if ((rc = run_forces(c, s, 1))) return rc;
+        if (per_step) {
+            timer_begin(c, TK_KICK);
+            rc = run_observe(c, s, c->obs_out + (size_t)k * REC);
+            timer_end(c, TK_KICK);
+            if (rc) return rc;
+        }
+    }
+    if (per_step && nsteps > 0) {
+        double *host = new (std::nothrow) double[(size_t)nsteps * REC];
+        if (!host) return SDPD_ENOMEM;
+        rc = check_hip(hipMemcpyAsync(host, c->obs_out, sizeof(double) * REC * (size_t)nsteps,
+                                      hipMemcpyDeviceToHost, c->stream));
+        int rc2 = take_error(c);
+        if (!rc)
+            for (int k = 0; k < nsteps; ++k) record_to_stats(host + (size_t)k * REC, &per_step[k]);
+        delete[] host;
+        return rc ? rc : rc2;
+    }
+    return SDPD_OK;
+}
+
+int sdpd_observe(sdpd_ctx *c, const sdpd_state *s, sdpd_stats *out)
+{
+    if (!c || !state_ok(c, s) || !out) return SDPD_EINVAL;
+    int rc = run_observe(c, s, c->obs_out);
+    if (rc) return rc;
+    double rec[REC];
+    if ((rc = check_hip(hipMemcpyAsync(rec, c->obs_out, sizeof rec, hipMemcpyDeviceToHost,
+                                       c->stream))))
+        return rc;
+    rc = take_error(c);
+    record_to_stats(rec, out);
+    return rc;
+}
+
+int sdpd_sync(sdpd_ctx *c)
+{
+    if (!c) return SDPD_EINVAL;
+    return take_error(c);
+}
+
+int sdpd_set_timing(sdpd_ctx *c, int enable)
+{
+    if (!c) return SDPD_EINVAL;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return SDPD_EHIP;
+    c->timing = enable != 0;
+    c->timer.used = 0;
+    return SDPD_OK;
+}
+
+int sdpd_timing(sdpd_ctx *c, double ms[5], int64_t launches[5])
+{
+    if (!c || !ms || !launches) return SDPD_EINVAL;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return SDPD_EHIP;
+    for (int k = 0; k < TK_N; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    Timer &T = c->timer;
+    for (size_t i = 0; i < T.used; i += 2) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, T.pool[i], T.pool[i + 1]) != hipSuccess) return SDPD_EHIP;
+        ms[T.cls[i / 2]] += t;
+        launches[T.cls[i / 2]] += 1;
+    }
+    T.used = 0;
+    return SDPD_OK;
+}
+
+int sdpd_tune(sdpd_ctx *c, int fd_tasks_intra, int fd_tasks_inter)
+{
+    if (!c || fd_tasks_intra < 1 || fd_tasks_inter < 1) return SDPD_EINVAL;
+    c->fd_tasks_intra = fd_tasks_intra;
+    c->fd_tasks_inter = fd_tasks_inter;
+    return SDPD_OK;
+}
+
+}  // extern "C"

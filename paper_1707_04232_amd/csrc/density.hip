@@ -1,0 +1,90 @@
+// SPH density, eq. (sdpd-rho-v), the entropy-conserving energy update of
+// Sec. 3.1, and the active-pair masks of the fluctuation/dissipation sweep.
+#include "sdpd_internal.hpp"
+
+namespace sdpd {
+
+// W(r) for r < h (Sec. 2.1.1; Lucy's kernel or the cubic spline of
+// eq. sdpd-cubic-w)
+__device__ __forceinline__ double kernel_w(const DevParams &P, double r)
+{
+    double x = r * P.inv_h;
+    double t = 1.0 - x;
+    if (P.kernel == SDPD_KERNEL_LUCY) return P.cW * (1.0 + 3.0 * x) * (t * t * t);
+    if (x <= 0.5) return P.cW * (1.0 - 6.0 * x * x + 6.0 * x * x * x);
+    return 2.0 * P.cW * (t * t * t);
+}
+
+// One thread per particle in cell order.  Candidates are the particles of
+// the 27 cells around the particle's cell, visited in the fixed order
+// (offset index 0..26 with z slowest, then slot), so the sum is
+// deterministic.  For the own cell and the 13 forward cells the bit of
+// every active partner's slot is stored: masks[k * n + i], k = 0 own cell
+// (partners other than i), k = 1..13 forward offsets 14..26.
+__global__ __launch_bounds__(256) void k_density(DevParams P, const double *__restrict__ q,
+                                                 const uint32_t *__restrict__ cell_sorted,
+                                                 const uint32_t *__restrict__ cell_start,
+                                                 double *rho, double *eps, int update_eps,
+                                                 uint64_t *__restrict__ masks,
+                                                 uint32_t *err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const int64_t n = P.n;
+    const uint32_t c = cell_sorted[i];
+    const int cx = (int)(c % (uint32_t)P.nc[0]);
+    const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
+    const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
+    const double xi = q[i], yi = q[n + i], zi = q[2 * n + i];
+    double acc = 0.0;
+    for (int k = 0; k < 27; ++k) {
+        int x2 = cx + (k % 3) - 1, y2 = cy + (k / 3) % 3 - 1, z2 = cz + k / 9 - 1;
+        x2 += x2 < 0 ? P.nc[0] : (x2 >= P.nc[0] ? -P.nc[0] : 0);
+        y2 += y2 < 0 ? P.nc[1] : (y2 >= P.nc[1] ? -P.nc[1] : 0);
+        z2 += z2 < 0 ? P.nc[2] : (z2 >= P.nc[2] ? -P.nc[2] : 0);
+        const uint32_t c2 = (uint32_t)(x2 + P.nc[0] * (y2 + P.nc[1] * z2));
+        const uint32_t s = cell_start[c2], e = cell_start[c2 + 1];
+        uint64_t mask = 0;
+        if (e - s > (uint32_t)P.cap) {   // overflowing cell: reported, not visited
+            atomicOr(err, ERR_CELLCAP);
+            if (k >= 13) masks[(int64_t)(k - 13) * n + i] = 0ull;
+            continue;
+        }
+        for (uint32_t j = s; j < e; ++j) {
+            double dx = min_image(xi - q[j], P.box[0], P.half_box[0]);
+            double dy = min_image(yi - q[n + j], P.box[1], P.half_box[1]);
+            double dz = min_image(zi - q[2 * n + j], P.box[2], P.half_box[2]);
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < P.h2) {
+                acc += P.m * kernel_w(P, sqrt(r2));
+                if (j != (uint32_t)i && j - s < (uint32_t)MAX_CAP) mask |= 1ull << (j - s);
+            }
+        }
+        if (k >= 13) masks[(int64_t)(k - 13) * n + i] = mask;
+    }
+    const double rho_old = rho[i];
+    rho[i] = acc;
+    if (update_eps) {
+        double e_new = eps[i] * pow(acc / rho_old, P.eps_exp);
+        if (!(e_new > 0.0) || !isfinite(e_new)) atomicOr(err, ERR_NONFINITE);
+        eps[i] = e_new;
+    }
+}
+
+int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps)
+{
+    if (c->n == 0) {
+        c->masks_valid = 1;
+        return SDPD_OK;
+    }
+    timer_begin(c, TK_DENSITY);
+    hipLaunchKernelGGL(k_density, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, c->stream,
+                       c->dp, s->q, c->cell_sorted, c->cell_start, s->rho, s->eps, update_eps,
+                       c->masks, c->err);
+    int rc = check_hip(hipGetLastError());
+    timer_end(c, TK_DENSITY);
+    if (!rc) c->masks_valid = 1;
+    return rc;
+}
+
+}  // namespace sdpd

@@ -1,0 +1,158 @@
+// Conservative pressure forces, eq. (cons-forces), fused with the second
+// half kick of eq. (sdpd-verlet); observables (Sec. 2.2.1).
+#include "sdpd_internal.hpp"
+
+namespace sdpd {
+
+// F(r) with grad W(r) = -F(|r|) r, for 0 < r < h (Sec. 2.1.1; the cubic
+// spline's second branch is 48/(pi h^4 r)(1 - r/h)^2)
+__device__ __forceinline__ double kernel_f(const DevParams &P, double r)
+{
+    double x = r * P.inv_h;
+    double t = 1.0 - x;
+    if (P.kernel == SDPD_KERNEL_LUCY) return P.cF * (t * t);
+    if (x <= 0.5) return P.cF * (2.0 - 3.0 * x);
+    return P.cF * P.h * (t * t) / r;
+}
+
+// P_i / rho_i^2 from the ideal-gas closure: A kB rho eps / (m Cv) / rho^2
+__global__ void k_pressure_term(DevParams P, const double *eps, const double *rho, double *pi)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n) pi[i] = P.cPi * eps[i] / rho[i];
+}
+
+// f_i = sum_{j != i, r < h} m^2 (Pi_i + Pi_j) F_ij r_ij, candidates in the
+// fixed 27-cell order; optionally p_i += dt/2 f_i.
+__global__ __launch_bounds__(256) void k_forces(DevParams P, const double *__restrict__ q,
+                                                const double *__restrict__ pi,
+                                                const uint32_t *__restrict__ cell_sorted,
+                                                const uint32_t *__restrict__ cell_start,
+                                                double *f, double *p, int half_kick,
+                                                uint32_t *err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const int64_t n = P.n;
+    const uint32_t c = cell_sorted[i];
+    const int cx = (int)(c % (uint32_t)P.nc[0]);
+    const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
+    const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
+    const double xi = q[i], yi = q[n + i], zi = q[2 * n + i];
+    const double pii = pi[i];
+    const double m2 = P.m * P.m;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int k = 0; k < 27; ++k) {
+        int x2 = cx + (k % 3) - 1, y2 = cy + (k / 3) % 3 - 1, z2 = cz + k / 9 - 1;
+        x2 += x2 < 0 ? P.nc[0] : (x2 >= P.nc[0] ? -P.nc[0] : 0);
+        y2 += y2 < 0 ? P.nc[1] : (y2 >= P.nc[1] ? -P.nc[1] : 0);
+        z2 += z2 < 0 ? P.nc[2] : (z2 >= P.nc[2] ? -P.nc[2] : 0);
+        const uint32_t c2 = (uint32_t)(x2 + P.nc[0] * (y2 + P.nc[1] * z2));
+        const uint32_t s = cell_start[c2], e = cell_start[c2 + 1];
+        if (e - s > (uint32_t)P.cap) {   // overflowing cell: reported, not visited
+            atomicOr(err, ERR_CELLCAP);
+            continue;
+        }
+        for (uint32_t j = s; j < e; ++j) {
+            double dx = min_image(xi - q[j], P.box[0], P.half_box[0]);
+            double dy = min_image(yi - q[n + j], P.box[1], P.half_box[1]);
+            double dz = min_image(zi - q[2 * n + j], P.box[2], P.half_box[2]);
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < P.h2 && j != (uint32_t)i) {
+                double sc = m2 * (pii + pi[j]) * kernel_f(P, sqrt(r2));
+                fx += sc * dx;
+                fy += sc * dy;
+                fz += sc * dz;
+            }
+        }
+    }
+    f[i] = fx;
+    f[n + i] = fy;
+    f[2 * n + i] = fz;
+    if (half_kick) {
+        const double hd = 0.5 * P.dt;
+        p[i] += hd * fx;
+        p[n + i] += hd * fy;
+        p[2 * n + i] += hd * fz;
+    }
+}
+
+int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick)
+{
+    if (c->n == 0) return SDPD_OK;
+    const unsigned g = (unsigned)((c->n + 255) / 256);
+    timer_begin(c, TK_FORCE);
+    hipLaunchKernelGGL(k_pressure_term, dim3(g), dim3(256), 0, c->stream, c->dp, s->eps, s->rho,
+                       c->pi);
+    hipLaunchKernelGGL(k_forces, dim3(g), dim3(256), 0, c->stream, c->dp, s->q, c->pi,
+                       c->cell_sorted, c->cell_start, s->f, s->p, half_kick, c->err);
+    int rc = check_hip(hipGetLastError());
+    timer_end(c, TK_FORCE);
+    return rc;
+}
+
+// --- observables: E_int, KE, P (3), min eps; deterministic two-level sums
+constexpr int OBS_THREADS = 256;
+constexpr int OBS_FIELDS = 6;
+
+__global__ __launch_bounds__(OBS_THREADS) void k_observe_partial(DevParams P, const double *p,
+                                                                 const double *eps,
+                                                                 double *partial)
+{
+    __shared__ double s[OBS_FIELDS][OBS_THREADS];
+    const int64_t n = P.n;
+    double v[OBS_FIELDS] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * OBS_THREADS + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * OBS_THREADS) {
+        double px = p[i], py = p[n + i], pz = p[2 * n + i];
+        v[0] += eps[i];
+        v[1] += (px * px + py * py + pz * pz) / (2.0 * P.m);
+        v[2] += px;
+        v[3] += py;
+        v[4] += pz;
+        v[5] = fmin(v[5], eps[i]);
+    }
+    for (int k = 0; k < OBS_FIELDS; ++k) s[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int off = OBS_THREADS / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            for (int k = 0; k < 5; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + off];
+            s[5][threadIdx.x] = fmin(s[5][threadIdx.x], s[5][threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < OBS_FIELDS) partial[blockIdx.x * OBS_FIELDS + threadIdx.x] = s[threadIdx.x][0];
+}
+
+
+__global__ void k_observe_final(const double *partial, int64_t nblocks,
+                                const unsigned long long *counters, double *rec)
+{
+    if (threadIdx.x != 0) return;
+    double v[OBS_FIELDS] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
+    for (int64_t b = 0; b < nblocks; ++b) {
+        for (int k = 0; k < 5; ++k) v[k] += partial[b * OBS_FIELDS + k];
+        v[5] = fmin(v[5], partial[b * OBS_FIELDS + 5]);
+    }
+    rec[0] = v[0] + v[1];
+    rec[1] = v[0];
+    rec[2] = v[1];
+    rec[3] = v[2];
+    rec[4] = v[3];
+    rec[5] = v[4];
+    rec[6] = v[5];
+    unsigned long long *ci = reinterpret_cast<unsigned long long *>(rec + 7);
+    for (int k = 0; k < CNT_N; ++k) ci[k] = counters[k];
+}
+
+int run_observe(sdpd_ctx *c, const sdpd_state *s, double *dst_record)
+{
+    if (c->n > 0)
+        hipLaunchKernelGGL(k_observe_partial, dim3((unsigned)c->obs_blocks), dim3(OBS_THREADS), 0,
+                           c->stream, c->dp, s->p, s->eps, c->obs_partial);
+    hipLaunchKernelGGL(k_observe_final, dim3(1), dim3(64), 0, c->stream, c->obs_partial,
+                       c->n > 0 ? c->obs_blocks : 0, c->counters, dst_record);
+    return check_hip(hipGetLastError());
+}
+
+}  // namespace sdpd

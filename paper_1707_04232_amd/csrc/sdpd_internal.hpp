@@ -1,0 +1,127 @@
+// Internal declarations of libsdpd (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "sdpd.h"
+
+namespace sdpd {
+
+// sticky device error bits
+enum : uint32_t { ERR_CELLCAP = 1u, ERR_NEGEPS = 2u, ERR_NONFINITE = 4u };
+
+// F/D counters, in this order in the device counter array
+enum { CNT_PROPOSED = 0, CNT_REJ_ENERGY, CNT_REJ_RATIO, CNT_MARGINAL, CNT_NEGEPS, CNT_N };
+
+// number of 64-bit active-pair masks per particle: slot 0 = own cell, slots
+// 1..13 = the 13 forward neighbour cells
+constexpr int NMASK = 14;
+constexpr int MAX_CAP = 64;
+
+// Everything a kernel needs, by value.  Derived constants are computed once
+// on the host.
+struct DevParams {
+    int64_t n;
+    double box[3], half_box[3], inv_cell[3];
+    int nc[3];
+    int64_t ncell;
+    double m, inv_m, h, h2, inv_h, kB, Cv, inv_Cv, A;
+    double dt;
+    int kernel, fd, cap;
+    uint32_t seed_lo, seed_hi, replica;
+    double cW;          // W prefactor: Lucy 105/(16 pi h^3), cubic 8/(pi h^3)
+    double cF;          // F prefactor: Lucy 315/(4 pi h^5), cubic 48/(pi h^5)
+    double cPi;         // P/rho^2 = cPi * eps / rho, cPi = A kB / (m Cv)
+    double eps_exp;     // A kB / Cv (constant-entropy exponent)
+    double kpar_c;      // (10/3 eta + 4 zeta) m^2
+    double kperp_c;     // (5/3 eta - zeta) m^2
+    double two_over_Cv; // 1/C_i + 1/C_j
+    double b2_c;        // 4 kB / m
+    double ent_c;       // Cv/kB - 1
+    double m_over_8, m_over_2;
+};
+
+// observable record (doubles): E, Eint, KE, P0, P1, P2, min_eps, then the
+// five F/D counters stored as 64-bit integers
+constexpr int REC = 12;
+
+// kernel timing classes
+enum { TK_CELLS = 0, TK_DENSITY, TK_FD, TK_FORCE, TK_KICK, TK_N };
+
+struct Timer {
+    std::vector<hipEvent_t> pool;
+    std::vector<int> cls;
+    size_t used = 0;
+};
+
+}  // namespace sdpd
+
+struct sdpd_ctx {
+    sdpd_params prm;
+    sdpd::DevParams dp;
+    hipStream_t stream;
+    int device;
+    int64_t n, ncell;
+    // cell list
+    uint32_t *cell_of, *count, *cursor, *cell_start, *block_sums, *tmp_idx, *perm, *cell_sorted;
+    int64_t nscan_blocks;
+    // gather targets of the sort (same shapes as the state)
+    double *tq, *tp, *teps, *trho, *tf;
+    uint32_t *tid;
+    double *pi;                  // P/rho^2 per particle
+    uint64_t *masks;             // NMASK * n
+    unsigned long long *counters;
+    uint32_t *err;
+    double *obs_partial;         // per-block observable partials
+    int64_t obs_blocks;
+    double *obs_out;             // device stats records
+    int64_t obs_cap;
+    int cells_valid, masks_valid;
+    int fd_tasks_intra, fd_tasks_inter;   // tasks per workgroup of the F/D kernel
+    sdpd::Timer timer;
+    int timing;
+    double last_fd_ms;
+    int64_t last_fd_launches;
+};
+
+namespace sdpd {
+
+int check_hip(hipError_t e);
+
+// host launchers (each returns an sdpd_status)
+int launch_fill_u32(sdpd_ctx *c, uint32_t *p, uint32_t v, int64_t n);
+int launch_fill_u64(sdpd_ctx *c, unsigned long long *p, unsigned long long v, int64_t n);
+int run_build_cells(sdpd_ctx *c, const sdpd_state *s, int kick_drift);
+int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps);
+int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick);
+int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, uint64_t step, double dt_fd);
+int run_observe(sdpd_ctx *c, const sdpd_state *s, double *dst_record);
+
+// event timing around one launch of class k (no-op unless c->timing)
+void timer_begin(sdpd_ctx *c, int k);
+void timer_end(sdpd_ctx *c, int k);
+
+}  // namespace sdpd
+
+// --------------------------------------------------------------- device helpers
+namespace sdpd {
+
+// minimum-image component (pairs within h never straddle half a box since
+// every box length is at least 4 h)
+__device__ __forceinline__ double min_image(double d, double box, double half)
+{
+    if (d > half) return d - box;
+    if (d < -half) return d + box;
+    return d;
+}
+
+__device__ __forceinline__ int cell_coord(double x, double inv_cell, int nc)
+{
+    int c = (int)floor(x * inv_cell);
+    return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
+}
+
+}  // namespace sdpd

@@ -1,12 +1,13 @@
-"""Seeded synthetic inputs: jittered cubic lattices in reduced units.
+"""Seeded synthetic inputs: jittered simple-cubic lattices in reduced units.
 
 This module only draws random inputs; it holds none of the method's
 arithmetic, so both the GPU path and the oracle may be fed from it.
 
-Recipe (the paper's setup of Sec. 4 restated in reduced units m = a = kB = 1):
-  * n_side^3 particles, site (i + 1/2) a of a simple cubic lattice, ids in
-    x-fastest lattice order, plus a uniform jitter U(-jitter, jitter) per
-    component;
+Recipe (the setup of Sec. 4 of the paper restated in reduced units
+m = a = kB = 1):
+  * nx * ny * nz particles on the sites (i + 1/2) a of a simple cubic
+    lattice, ids in x-fastest lattice order, plus a uniform jitter
+    U(-jitter, jitter) per component; box = (nx, ny, nz) a;
   * momenta Maxwell-Boltzmann at temperature T: N(0, m kB T) per component,
     minus the mean so that the total momentum is zero;
   * internal energies eps_i = Cv T (so that T_i = T for the ideal gas).
@@ -19,7 +20,7 @@ import numpy as np
 @dataclass(frozen=True)
 class Workload:
     name: str
-    n_side: int
+    dims: tuple
     Cv: float
     T: float
     steps: int
@@ -36,31 +37,36 @@ class Workload:
 
     @property
     def n(self) -> int:
-        return self.n_side ** 3
+        return int(np.prod(self.dims))
 
     @property
-    def box(self) -> float:
-        return self.n_side * self.spacing
+    def box(self) -> tuple:
+        return tuple(float(d * self.spacing) for d in self.dims)
 
 
-# The five synthetic workloads (sizes of the paper's setting scaled up).
+# Synthetic workloads.  The 1M and 8M boxes hold N = 2^20 and 2^23 particles
+# on 128 x 128 x 64 and 256 x 256 x 128 lattices.
 WORKLOADS = {
-    "lattice10_cv10": Workload("lattice10_cv10", 10, Cv=10.0, T=1.0, steps=100),
-    "lattice128_cv1.5_T0.1": Workload("lattice128_cv1.5_T0.1", 128, Cv=1.5, T=0.1, steps=1000),
-    "lattice256_cv10": Workload("lattice256_cv10", 256, Cv=10.0, T=1.0, steps=200),
-    "lattice64_cv10": Workload("lattice64_cv10", 64, Cv=10.0, T=1.0, steps=50),
+    "lattice10_cv10": Workload("lattice10_cv10", (10, 10, 10), Cv=10.0, T=1.0, steps=100),
+    "lattice128x128x64_cv1.5_T0.1": Workload("lattice128x128x64_cv1.5_T0.1", (128, 128, 64),
+                                             Cv=1.5, T=0.1, steps=1000),
+    "lattice256x256x128_cv10": Workload("lattice256x256x128_cv10", (256, 256, 128),
+                                        Cv=10.0, T=1.0, steps=200),
+    "lattice64_cv10": Workload("lattice64_cv10", (64, 64, 64), Cv=10.0, T=1.0, steps=50),
 }
 
 
-def lattice_state(n_side: int, spacing: float = 1.0, jitter: float = 0.05, m: float = 1.0,
+def lattice_state(dims, spacing: float = 1.0, jitter: float = 0.05, m: float = 1.0,
                   kB: float = 1.0, T: float = 1.0, Cv: float = 10.0, seed: int = 0):
-    """Returns q (3, N), p (3, N), eps (N,), id (N,) as numpy arrays."""
-    n = n_side ** 3
+    """Returns q (3, N), p (3, N), eps (N,), id (N,) as numpy arrays.
+    dims: an int (cube) or (nx, ny, nz)."""
+    nx, ny, nz = (dims,) * 3 if np.ndim(dims) == 0 else tuple(dims)
+    n = nx * ny * nz
     rng = np.random.default_rng(seed)
     k = np.arange(n)
-    site = np.stack([k % n_side, (k // n_side) % n_side, k // (n_side * n_side)]).astype(np.float64)
+    site = np.stack([k % nx, (k // nx) % ny, k // (nx * ny)]).astype(np.float64)
     q = (site + 0.5) * spacing + rng.uniform(-jitter, jitter, size=(3, n))
-    L = n_side * spacing
+    L = np.array([nx, ny, nz], np.float64)[:, None] * spacing
     q = np.where(q >= L, q - L, np.where(q < 0.0, q + L, q))
     p = rng.normal(0.0, np.sqrt(m * kB * T), size=(3, n))
     p -= p.mean(axis=1, keepdims=True)
@@ -70,11 +76,24 @@ def lattice_state(n_side: int, spacing: float = 1.0, jitter: float = 0.05, m: fl
 
 
 def workload_state(w: Workload):
-    return lattice_state(w.n_side, w.spacing, w.jitter, w.m, w.kB, w.T, w.Cv, w.init_seed)
+    return lattice_state(w.dims, w.spacing, w.jitter, w.m, w.kB, w.T, w.Cv, w.init_seed)
+
+
+def uniform_state(n: int, box, T: float = 1.0, Cv: float = 10.0, m: float = 1.0,
+                  kB: float = 1.0, seed: int = 0):
+    """n particles uniformly at random in a (possibly non-cubic) box."""
+    rng = np.random.default_rng(seed)
+    L = np.asarray(box, np.float64).reshape(3, 1)
+    q = rng.uniform(0.0, 1.0, size=(3, n)) * L
+    p = rng.normal(0.0, np.sqrt(m * kB * T), size=(3, n))
+    if n:
+        p -= p.mean(axis=1, keepdims=True)
+    return np.ascontiguousarray(q), np.ascontiguousarray(p), np.full(n, Cv * T), \
+        np.arange(n, dtype=np.uint32)
 
 
 def shuffled(q, p, eps, ids, seed: int = 1):
-    """The same particles in a random storage order (for order-independence checks)."""
+    """The same particles in a random storage order."""
     perm = np.random.default_rng(seed).permutation(eps.shape[0])
     return (np.ascontiguousarray(q[:, perm]), np.ascontiguousarray(p[:, perm]),
             eps[perm].copy(), ids[perm].copy())
