@@ -1,0 +1,168 @@
+"""Throughput benchmark: full SDPD steps (Velocity-Verlet with density and
+pressure forces + one Metropolized F/D sweep) on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line: particle-steps/s over the K timed steps, the energy
+drift per 1000 steps, the roofline of the dominant kernel (the F/D phase
+kernel, timed with HIP events on the library's stream during the timed
+steps) and the oracle's single-core rate on a bounded sample.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "lattice128x128x64_cv1.5_T0.1"
+
+# FP64 VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+FP64_VALU_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+# Algorithmic FP64 work of one EMS pair update, in flops (FMA = 2); every
+# elementary function is weighted by the FP64 operations of its gfx950
+# implementation.  Derivation in the design notes.
+FLOPS_PER_EMS_PAIR = 1000.0
+
+
+def linear_slope(y):
+    x = np.arange(len(y), dtype=np.float64)
+    x -= x.mean()
+    return float((x * (y - y.mean())).sum() / (x * x).sum())
+
+
+def cpu_baseline(w, sample_dims=(64, 64, 64)):
+    """The oracle as it stands: one full step of the same workload on a
+    sub-lattice of sample_dims (same density, heat capacity, temperature,
+    time step), single threaded."""
+    import oracle as O
+    from paper_1707_04232_amd.workload import lattice_state
+    q, p, eps, ids = lattice_state(sample_dims, Cv=w.Cv, T=w.T, seed=w.init_seed)
+    n = len(eps)
+    P = O.OracleParams(n=n, box=tuple(float(d) for d in sample_dims), Cv=w.Cv, dt=w.dt,
+                       eta=w.eta, zeta=w.zeta, h=w.h, m=w.m, kB=w.kB, seed=w.seed)
+    S = O.State.from_arrays(q, p, eps, ids)
+    O.prepare(P, S)
+    t0 = time.perf_counter()
+    rc, _ = O.step(P, S, 0, 1)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 full step (cells, density, EMS sweep, forces) of the same workload on a "
+                      f"{sample_dims[0]}x{sample_dims[1]}x{sample_dims[2]} sub-lattice "
+                      f"({n} particles), {dt:.1f} s, rc={rc}",
+            "cpu": platform.processor() or platform.machine()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="do not bracket kernels with HIP events")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (a known-traffic "
+                         "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is described in the design notes, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1707_04232_amd import sdpd
+    from paper_1707_04232_amd.workload import WORKLOADS, workload_state
+
+    w = WORKLOADS[WORKLOAD]
+    torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr,
+              flush=True)
+        del src, dst
+    q, p, eps, ids = workload_state(w)
+    S = sdpd.DeviceState.from_numpy(q, p, eps, ids)
+    prm = sdpd.SdpdParams(n=w.n, box=w.box, m=w.m, h=w.h, kB=w.kB, Cv=w.Cv, eta=w.eta,
+                          zeta=w.zeta, dt=w.dt, fd=sdpd.FD_EMS, seed=w.seed)
+    ctx = sdpd.Context(prm)
+    ctx.prepare(S)
+    print(f"# {WORKLOAD}: n={w.n}, warmup {args.warmup}, timed {args.steps}", file=sys.stderr,
+          flush=True)
+    if args.warmup:
+        ctx.step(S, 0, args.warmup, stats=False)
+    ctx.sync()
+    ctx.set_timing(not args.no_timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.step(S, args.warmup, args.steps, stats=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = ctx.timing()
+    ctx.set_timing(False)
+    ctx.sync()
+    elapsed = t1 - t0
+    value = w.n * args.steps / elapsed
+
+    E = np.array([s["E"] for s in st])
+    proposed = sum(s["proposed"] for s in st)
+    rej_e = sum(s["rej_energy"] for s in st)
+    rej_r = sum(s["rej_ratio"] for s in st)
+    slope = linear_slope(E) if len(E) > 1 else 0.0
+    drift = {"per_1e3_steps_per_particle_kBT": slope * 1000.0 / (w.n * w.kB * w.T),
+             "per_1e3_steps_relative": slope * 1000.0 / abs(E[0]),
+             "E0": float(E[0]), "E_last": float(E[-1])}
+
+    roof = None
+    fd_ms, fd_launches = tm["fd"]
+    if fd_launches:
+        avg_ms = fd_ms / fd_launches
+        flops_per_launch = FLOPS_PER_EMS_PAIR * proposed / fd_launches
+        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "k_fd_phase", "achieved": achieved,
+                "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                "avg_launch_ms": avg_ms, "launches": fd_launches,
+                "pairs_per_launch": proposed / fd_launches}
+    breakdown = {k: {"ms_per_step": v[0] / args.steps, "launches": v[1]}
+                 for k, v in tm.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w)
+
+    out = {
+        "metric": "particle-steps/s (full SDPD step) at 1M particles; energy drift per 1e3 steps",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": w.n, "lattice": list(w.dims), "box": list(w.box),
+                   "Cv": w.Cv, "T": w.T, "dt": w.dt, "h": w.h, "kernel": "lucy",
+                   "fd": "EMS", "steps": args.steps},
+        "energy_drift": drift,
+        "fd": {"pairs_per_step": proposed / args.steps,
+               "rejection_rate": (rej_e + rej_r) / max(proposed, 1),
+               "rej_energy": rej_e, "rej_ratio": rej_r},
+        "kernel_ms_per_step": breakdown,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

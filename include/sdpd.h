@@ -39,7 +39,8 @@ typedef enum {
     SDPD_ENOMEM = -3,     /* workspace allocation failed                      */
     SDPD_ECELLCAP = -4,   /* a cell holds more than cell_cap particles        */
     SDPD_ENEGEPS = -5,    /* SSA mode produced eps <= 0 (Sec. 3.2 of the paper) */
-    SDPD_ENONFINITE = -6  /* a position, energy or density is not finite      */
+    SDPD_ENONFINITE = -6, /* a position, energy or density is not finite      */
+    SDPD_ECAPACITY = -7   /* more active pairs than the schedule holds (64 per particle) */
 } sdpd_status;
 
 /* SPH kernel W with support h (Sec. 2.1.1): Lucy's quartic, or the paper's
@@ -182,9 +183,10 @@ int sdpd_set_timing(sdpd_ctx *ctx, int enable);
 int sdpd_timing(sdpd_ctx *ctx, double ms[5], int64_t launches[5]);
 
 /* Execution-only tuning of the F/D sweep (results do not change): tasks
- * (cells, resp. cell pairs) given to one workgroup in phase 0 and in the
- * inter-cell phases.  Both >= 1.                                          */
-int sdpd_tune(sdpd_ctx *ctx, int fd_tasks_intra, int fd_tasks_inter);
+ * given to one workgroup in phase 0 (cells) and in the face, edge and corner
+ * phases (cell pairs whose offset has 1, 2, 3 non-zero components).  Each
+ * in 1..64.                                                              */
+int sdpd_tune(sdpd_ctx *ctx, const int32_t fd_tasks[4]);
 
 const char *sdpd_strerror(int status);
 int sdpd_abi_version(void);

@@ -135,7 +135,9 @@ static void free_ctx(sdpd_ctx *c)
 {
     void *bufs[] = {c->cell_of, c->count, c->cursor, c->cell_start, c->block_sums, c->tmp_idx,
                     c->perm, c->cell_sorted, c->tq, c->tp, c->teps, c->trho, c->tf, c->tid,
-                    c->pi, c->masks, c->counters, c->err, c->obs_partial, c->obs_out};
+                    c->pi, c->masks, c->counters, c->err, c->obs_partial, c->obs_out,
+                    c->dparams, c->task_count, c->task_np, c->pair_off, c->part_off,
+                    c->part_list, c->pairs};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
@@ -161,6 +163,7 @@ static int take_error(sdpd_ctx *c)
     }
     if (e & ERR_CELLCAP) return SDPD_ECELLCAP;
     if (e & ERR_NONFINITE) return SDPD_ENONFINITE;
+    if (e & ERR_PAIRCAP) return SDPD_ECAPACITY;
     if (e & ERR_NEGEPS) return SDPD_ENEGEPS;
     return SDPD_OK;
 }
@@ -212,6 +215,7 @@ const char *sdpd_strerror(int s)
     case SDPD_ECELLCAP: return "a cell holds more particles than cell_cap";
     case SDPD_ENEGEPS: return "non-positive internal energy (SSA)";
     case SDPD_ENONFINITE: return "non-finite or non-positive state value";
+    case SDPD_ECAPACITY: return "pair schedule capacity exceeded";
     default: return "unknown status";
     }
 }
@@ -235,10 +239,16 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     c->n = params->n;
     c->ncell = c->dp.ncell;
     const size_t n = (size_t)c->n, nce = (size_t)c->ncell;
-    c->nscan_blocks = (int64_t)((nce + 1023) / 1024);
+    c->nscan_blocks = (int64_t)(((size_t)NMASK * nce + 1023) / 1024) + 1;
     c->obs_blocks = c->n > 0 ? std::min<int64_t>(1024, (c->n + 255) / 256) : 1;
-    c->fd_tasks_intra = 16;
-    c->fd_tasks_inter = 8;
+    c->fd_tasks[0] = 7;
+    c->fd_tasks[1] = 8;
+    c->fd_tasks[2] = 16;
+    c->fd_tasks[3] = 40;
+    // schedule capacity: 64 pairs per particle (a jittered lattice has ~39),
+    // and at most 27 list entries per particle (1 own-cell + 2 x 13 tasks)
+    c->pair_cap = std::max<int64_t>(64 * c->n, 1024);
+    c->part_cap = std::max<int64_t>(27 * c->n, 1024);
     rc = SDPD_OK;
     rc = rc ? rc : dalloc(&c->cell_of, n);
     rc = rc ? rc : dalloc(&c->count, nce);
@@ -260,6 +270,16 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     rc = rc ? rc : dalloc(&c->err, 1);
     rc = rc ? rc : dalloc(&c->obs_partial, (size_t)c->obs_blocks * 6);
     rc = rc ? rc : ensure_records(c, 64);
+    rc = rc ? rc : dalloc(&c->dparams, 1);
+    rc = rc ? rc : dalloc(&c->task_count, (size_t)NMASK * nce);
+    rc = rc ? rc : dalloc(&c->task_np, (size_t)NMASK * nce);
+    rc = rc ? rc : dalloc(&c->pair_off, (size_t)NMASK * nce + 1);
+    rc = rc ? rc : dalloc(&c->part_off, (size_t)NMASK * nce + 1);
+    rc = rc ? rc : dalloc(&c->pairs, (size_t)c->pair_cap);
+    rc = rc ? rc : dalloc(&c->part_list, (size_t)c->part_cap);
+    if (!rc)
+        rc = check_hip(hipMemcpyAsync(c->dparams, &c->dp, sizeof c->dp, hipMemcpyHostToDevice,
+                                      c->stream));
     if (!rc) rc = launch_fill_u32(c, c->err, 0u, 1);
     if (!rc) rc = launch_fill_u64(c, c->counters, 0ull, CNT_N);
     if (!rc) rc = check_hip(hipStreamSynchronize(c->stream));
@@ -416,11 +436,12 @@ int sdpd_timing(sdpd_ctx *c, double ms[5], int64_t launches[5])
     return SDPD_OK;
 }
 
-int sdpd_tune(sdpd_ctx *c, int fd_tasks_intra, int fd_tasks_inter)
+int sdpd_tune(sdpd_ctx *c, const int32_t fd_tasks[4])
 {
-    if (!c || fd_tasks_intra < 1 || fd_tasks_inter < 1) return SDPD_EINVAL;
-    c->fd_tasks_intra = fd_tasks_intra;
-    c->fd_tasks_inter = fd_tasks_inter;
+    if (!c || !fd_tasks) return SDPD_EINVAL;
+    for (int k = 0; k < 4; ++k)
+        if (fd_tasks[k] < 1 || fd_tasks[k] > 64) return SDPD_EINVAL;
+    for (int k = 0; k < 4; ++k) c->fd_tasks[k] = fd_tasks[k];
     return SDPD_OK;
 }
 

@@ -83,7 +83,7 @@ __global__ void k_scan_local(const uint32_t *count, int64_t ncell, int cap, uint
 #pragma unroll
     for (int k = 0; k < SCAN_PER_THREAD; ++k) {
         v[k] = base + k < ncell ? count[base + k] : 0u;
-        over = over || v[k] > (uint32_t)cap;
+        over = over || (cap >= 0 && v[k] > (uint32_t)cap);
         sum += v[k];
     }
     if (over) atomicOr(err, ERR_CELLCAP);
@@ -97,7 +97,8 @@ __global__ void k_scan_local(const uint32_t *count, int64_t ncell, int cap, uint
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
-// one workgroup: exclusive scan of the block sums, in place
+// one workgroup: exclusive scan of the block sums, in place; the grand
+// total goes to block_sums[nblocks]
 __global__ void k_scan_sums(uint32_t *block_sums, int64_t nblocks)
 {
     __shared__ uint32_t s[SCAN_THREADS];
@@ -110,16 +111,34 @@ __global__ void k_scan_sums(uint32_t *block_sums, int64_t nblocks)
         if (i < nblocks) block_sums[i] = ex + carry;
         carry += total;
     }
+    if (threadIdx.x == 0) block_sums[nblocks] = carry;
 }
 
-__global__ void k_scan_add(uint32_t *out, const uint32_t *block_sums, int64_t ncell, uint32_t n)
+__global__ void k_scan_add(uint32_t *out, const uint32_t *block_sums, int64_t count,
+                           int64_t nblocks)
 {
     int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_PER_THREAD;
     uint32_t add = block_sums[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < SCAN_PER_THREAD; ++k)
-        if (base + k < ncell) out[base + k] += add;
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[ncell] = n;
+        if (base + k < count) out[base + k] += add;
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[count] = block_sums[nblocks];
+}
+
+// out[0..count] = exclusive prefix sums of in[0..count), out[count] = total.
+// block_sums needs ceil(count / 1024) + 1 entries.  A value above cap sets
+// ERR_CELLCAP (cap < 0: no check).
+int run_scan(sdpd_ctx *c, const uint32_t *in, uint32_t *out, int64_t count, uint32_t *block_sums,
+             int cap)
+{
+    const int64_t nb = (count + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    if (nb == 0) return launch_fill_u32(c, out, 0u, 1);
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, c->stream, in,
+                       count, cap, out, block_sums, c->err);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, c->stream, block_sums, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, c->stream, out,
+                       block_sums, count, nb);
+    return check_hip(hipGetLastError());
 }
 
 // particle i goes to an arbitrary free position of its cell
@@ -209,14 +228,7 @@ int run_build_cells(sdpd_ctx *c, const sdpd_state *s, int kick_drift)
                            c->dp, s->q, s->p, s->f, kick_drift, c->cell_of, c->count, c->err);
         if ((rc = check_hip(hipGetLastError()))) return rc;
     }
-    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)c->nscan_blocks), dim3(SCAN_THREADS), 0,
-                       c->stream, c->count, nc, c->prm.cell_cap, c->cell_start, c->block_sums,
-                       c->err);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, c->stream, c->block_sums,
-                       c->nscan_blocks);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)c->nscan_blocks), dim3(SCAN_THREADS), 0,
-                       c->stream, c->cell_start, c->block_sums, nc, (uint32_t)n);
-    if ((rc = check_hip(hipGetLastError()))) return rc;
+    if ((rc = run_scan(c, c->count, c->cell_start, nc, c->block_sums, c->prm.cell_cap))) return rc;
     if (n > 0) {
         unsigned g = blocks_for(n, 256);
         hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, c->stream, c->cell_of, c->cell_start,

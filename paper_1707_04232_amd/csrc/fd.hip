@@ -13,451 +13,233 @@
 // pairs of one round share no particle, so any schedule that keeps the key
 // order between pairs sharing a particle gives the same result.
 //
-// GPU schedule.  One launch per phase.  A workgroup of one wave takes a
-// batch of tasks, stages their particles in LDS, and for each task walks
-// the rounds that have an active pair: lane x holds slot x of A and of B,
-// the partner of slot x in round s is x ^ s (a lane shuffle), and each pair
-// gets the level 1 + max(level of the previous pair of either particle).
-// Pairs of one level share no particle, so the wave then applies the
-// pending pairs of all its tasks level by level, 64 at a time.
-#include "sdpd_internal.hpp"
+// GPU schedule.  The scheduling pass (schedule.hip) has stored, for every
+// task, its active pairs with their conflict level.  One launch per phase:
+// a workgroup of one wave takes a batch of consecutive tasks of the phase,
+// stages in LDS only the particles that take part in a pair, sorts the
+// batch's pairs by level and applies the pairs of one level (which share no
+// particle) as parallel steps of 64 lanes.
+#include "fd_math.hpp"
 
 namespace sdpd {
 
-constexpr int FD_MAXP = 256;       // particles staged per batch
-constexpr int FD_MAXPAIRS = 1024;  // pending pairs per flush
 constexpr int FD_MAXTASKS = 64;    // tasks per batch
-constexpr int FD_NLVL = 64;        // levels are 1..64 between flushes
+constexpr int FD_NLVL = 64;        // levels of a task are 1..64
 
 struct FdPhase {
     int phase;          // 0..104
-    int mslot;          // mask slot of the B cell (0 = own cell)
+    int mslot;          // mask / task slot of the phase (0 = own cell)
     int d[3];           // offset of B relative to A
     int par[3];         // coordinate parity of A
     int hx, hy;         // tasks per axis (x, y) of a parity class
     int64_t ntasks;
     int64_t tasks_per_wg;
+    int64_t task_base;  // index of the phase's first task in sweep order
 };
 
-// ---------------------------------------------------------------- Philox
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
-// 32x32->64 products with multipliers 0xD2511F53 and 0xCD9E8D57, key
-// advanced by the Weyl constants 0x9E3779B9 and 0xBB67AE85 between rounds.
-__device__ __forceinline__ void philox4x32_10(uint32_t &x0, uint32_t &x1, uint32_t &x2,
-                                              uint32_t &x3, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t a = (uint64_t)0xD2511F53u * x0;
-        const uint64_t b = (uint64_t)0xCD9E8D57u * x2;
-        const uint32_t y0 = (uint32_t)(b >> 32) ^ x1 ^ k0;
-        const uint32_t y2 = (uint32_t)(a >> 32) ^ x3 ^ k1;
-        x1 = (uint32_t)b;
-        x3 = (uint32_t)a;
-        x0 = y0;
-        x2 = y2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
-__device__ __forceinline__ double open_unit(uint32_t w)
-{
-    return ((double)w + 0.5) * 2.3283064365386962890625e-10;  // (w + 1/2) 2^-32
-}
-
-// Gaussian vector (Box-Muller on the first block) and uniform of one pair
-__device__ __forceinline__ void pair_draws(const DevParams &P, uint32_t step, uint32_t id_i,
-                                           uint32_t id_j, double G[3], double &U)
-{
-    uint32_t a0 = step, a1 = id_i, a2 = id_j, a3 = P.replica * 2u;
-    uint32_t b0 = step, b1 = id_i, b2 = id_j, b3 = P.replica * 2u + 1u;
-    philox4x32_10(a0, a1, a2, a3, P.seed_lo, P.seed_hi);
-    philox4x32_10(b0, b1, b2, b3, P.seed_lo, P.seed_hi);
-    const double R1 = sqrt(-2.0 * log(open_unit(a0)));
-    const double R2 = sqrt(-2.0 * log(open_unit(a2)));
-    double s1, c1;
-    sincospi(2.0 * open_unit(a1), &s1, &c1);
-    G[0] = R1 * c1;
-    G[1] = R1 * s1;
-    G[2] = R2 * cospi(2.0 * open_unit(a3));
-    U = open_unit(b0);
-}
-
-// ---------------------------------------------------------------- coefficients
-// alpha^theta and the squared relative-velocity noise amplitude
-// b^theta^2 = ((2/m) zeta^theta)^2 at energies (ei, ej).  With
-// gamma = kappa (1 - d) and sigma^2 = 4 kappa kB T_i T_j/(T_i + T_j) of
-// eq. (sdpd-gamma-sigma), zeta^2 = sigma^2 m (1 - alpha^2)/(4 gamma) reduces
-// to m kB T_red (1 - alpha^2)/(1 - d) with T_red = T_i T_j/(T_i + T_j), so
-// b^2 = (4 kB/m) T_red (1 - alpha^2)/(1 - d).  With e = expm1(-2 gamma dt/m):
-// alpha = 1 + e and 1 - alpha^2 = -e (2 + e), both without cancellation.
-struct Coef {
-    double al_par, al_perp, b2_par, b2_perp;
-};
-
-__device__ __forceinline__ Coef fd_coef(const DevParams &P, double kpar, double kperp, double ei,
-                                        double ej, double dt)
-{
-    const double Ti = ei * P.inv_Cv, Tj = ej * P.inv_Cv;
-    const double inv_Ts = 1.0 / (Ti + Tj);
-    const double Tred = Ti * Tj * inv_Ts;
-    const double d = P.kB * Tred * inv_Ts * P.two_over_Cv;
-    const double omd = 1.0 - d;
-    const double c = -2.0 * dt * P.inv_m * omd;
-    const double e_par = expm1(c * kpar), e_perp = expm1(c * kperp);
-    const double s = P.b2_c * Tred / omd;
-    Coef r;
-    r.al_par = 1.0 + e_par;
-    r.al_perp = 1.0 + e_perp;
-    r.b2_par = -s * e_par * (2.0 + e_par);
-    r.b2_perp = -s * e_perp * (2.0 + e_perp);
-    return r;
-}
-
-struct FdCount {
-    uint32_t proposed, rej_energy, rej_ratio, marginal, negeps;
-};
-
-// One pair update on LDS-resident state; li has the smaller id.
-__device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, double dt, int li,
-                                        int lj, double (*s_q)[FD_MAXP], double (*s_p)[FD_MAXP],
-                                        double *s_eps, const double *s_rho,
-                                        const uint32_t *s_id, FdCount &cnt, bool &negeps)
-{
-    // geometry (Sec. 2.1.1): r_ij, e_ij, F_ij
-    const double dx = min_image(s_q[0][li] - s_q[0][lj], P.box[0], P.half_box[0]);
-    const double dy = min_image(s_q[1][li] - s_q[1][lj], P.box[1], P.half_box[1]);
-    const double dz = min_image(s_q[2][li] - s_q[2][lj], P.box[2], P.half_box[2]);
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    const double inv_r = 1.0 / r;
-    const double ex = dx * inv_r, ey = dy * inv_r, ez = dz * inv_r;
-    const double x = r * P.inv_h, t = 1.0 - x;
-    double F;
-    if (P.kernel == SDPD_KERNEL_LUCY) F = P.cF * (t * t);
-    else F = x <= 0.5 ? P.cF * (2.0 - 3.0 * x) : P.cF * P.h * (t * t) * inv_r;
-    // kappa^theta of Sec. 2.2.2
-    const double kfac = F / (s_rho[li] * s_rho[lj]);
-    const double kpar = P.kpar_c * kfac, kperp = P.kperp_c * kfac;
-
-    const double ei = s_eps[li], ej = s_eps[lj];
-    const double vx = (s_p[0][li] - s_p[0][lj]) * P.inv_m;
-    const double vy = (s_p[1][li] - s_p[1][lj]) * P.inv_m;
-    const double vz = (s_p[2][li] - s_p[2][lj]) * P.inv_m;
-
-    double G[3], U;
-    pair_draws(P, step, s_id[li], s_id[lj], G, U);
-
-    // proposal, eq. (proposal): v' = A(v) v + B(v) G, B = (2/m) zeta^theta P^theta
-    const Coef f = fd_coef(P, kpar, kperp, ei, ej, dt);
-    const double b_par = sqrt(f.b2_par), b_perp = sqrt(f.b2_perp);
-    const double vpar = vx * ex + vy * ey + vz * ez;
-    const double Gpar = G[0] * ex + G[1] * ey + G[2] * ez;
-    const double vqx = vx - vpar * ex, vqy = vy - vpar * ey, vqz = vz - vpar * ez;
-    const double Gqx = G[0] - Gpar * ex, Gqy = G[1] - Gpar * ey, Gqz = G[2] - Gpar * ez;
-    const double npar = f.al_par * vpar + b_par * Gpar;
-    const double nqx = f.al_perp * vqx + b_perp * Gqx;
-    const double nqy = f.al_perp * vqy + b_perp * Gqy;
-    const double nqz = f.al_perp * vqz + b_perp * Gqz;
-    const double nvx = npar * ex + nqx, nvy = npar * ey + nqy, nvz = npar * ez + nqz;
-    // energy change, eq. (proposal-update)
-    const double delta = P.m_over_8 * ((nvx * nvx + nvy * nvy + nvz * nvz)
-                                       - (vx * vx + vy * vy + vz * vz));
-    const double emin = fmin(ei, ej);
-    bool accept = true;
-    cnt.proposed += 1;
-    if (P.fd == SDPD_FD_SSA) {
-        if (!(ei - delta > 0.0 && ej - delta > 0.0)) {
-            cnt.negeps += 1;
-            negeps = true;
-        }
-    } else {
-        if (fabs(emin - delta) <= 1e-12 * fmax(fabs(emin), fabs(delta))) cnt.marginal += 1;
-        if (!(emin > delta)) {                       // eq. (energy-bound)
-            accept = false;
-            cnt.rej_energy += 1;
-        } else if (P.fd == SDPD_FD_EMS) {
-            // reverse move from v' at the proposed energies, eq. (metropolis-ratio)
-            const double ei2 = ei - delta, ej2 = ej - delta;
-            const Coef g = fd_coef(P, kpar, kperp, ei2, ej2, dt);
-            const double wpar = vpar - g.al_par * npar;
-            const double wqx = vqx - g.al_perp * nqx;
-            const double wqy = vqy - g.al_perp * nqy;
-            const double wqz = vqz - g.al_perp * nqz;
-            const double quad = wpar * wpar / g.b2_par + (wqx * wqx + wqy * wqy + wqz * wqz) / g.b2_perp;
-            const double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
-            // log|B(v)| - log|B(v')| = (1/2) log(b_par^2 b_perp^4 / (b'_par^2 b'_perp^4))
-            const double logdet = 0.5 * log((f.b2_par * f.b2_perp * f.b2_perp)
-                                            / (g.b2_par * g.b2_perp * g.b2_perp));
-            // ideal gas: sum_k (S(eps'_k) - S(eps_k))/kB - log T(eps'_k) + log T(eps_k)
-            //          = (Cv/kB - 1) log((1 - delta/ei)(1 - delta/ej))
-            const double ui = -delta / ei, uj = -delta / ej;
-            const double ent = P.ent_c * log1p(ui + uj + ui * uj);
-            const double a = 0.5 * G2 - 0.5 * quad + logdet + ent;
-            const double lnU = log(U);
-            if (fabs(a - lnU) <= 1e-9) cnt.marginal += 1;
-            if (!(lnU <= a)) {                       // reject iff U > exp(a)
-                accept = false;
-                cnt.rej_ratio += 1;
-            }
-        }
-    }
-    if (accept) {
-        const double hm = P.m_over_2;
-        const double dpx = hm * (nvx - vx), dpy = hm * (nvy - vy), dpz = hm * (nvz - vz);
-        s_p[0][li] += dpx;
-        s_p[1][li] += dpy;
-        s_p[2][li] += dpz;
-        s_p[0][lj] -= dpx;
-        s_p[1][lj] -= dpy;
-        s_p[2][lj] -= dpz;
-        s_eps[li] = ei - delta;
-        s_eps[lj] = ej - delta;
-    }
-}
-
-// ---------------------------------------------------------------- wave helpers
-__device__ __forceinline__ uint64_t xor_permute_bits(uint64_t m, uint32_t x)
-{
-    // bit b of m moves to bit b ^ x
-    const uint64_t M[6] = {0x5555555555555555ull, 0x3333333333333333ull,
-                           0x0F0F0F0F0F0F0F0Full, 0x00FF00FF00FF00FFull,
-                           0x0000FFFF0000FFFFull, 0x00000000FFFFFFFFull};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const int sh = 1 << k;
-        const uint64_t sw = ((m & M[k]) << sh) | ((m >> sh) & M[k]);
-        m = ((x >> k) & 1u) ? sw : m;
-    }
-    return m;
-}
-
-__device__ __forceinline__ uint64_t wave_or64(uint64_t v)
-{
-    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        lo |= (uint32_t)__shfl_xor((int)lo, off);
-        hi |= (uint32_t)__shfl_xor((int)hi, off);
-    }
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off);
-    return v;
-}
-
-// ---------------------------------------------------------------- the phase kernel
+template <int MAXP, int MAXPAIRS>
 struct FdShared {
-    double q[3][FD_MAXP];
-    double p[3][FD_MAXP];
-    double eps[FD_MAXP];
-    double rho[FD_MAXP];
-    uint32_t id[FD_MAXP];
-    uint32_t gidx[FD_MAXP];
-    uint32_t pair[FD_MAXPAIRS];
-    uint32_t sorted[FD_MAXPAIRS];
-    uint8_t lvl[FD_MAXPAIRS];
-    uint32_t hist[FD_NLVL + 1];
+    double q[3][MAXP];
+    double p[3][MAXP];
+    double eps[MAXP];
+    double rho[MAXP];
+    uint32_t id[MAXP];
+    uint32_t gidx[MAXP];
+    uint32_t sorted[MAXPAIRS];       // batch particle index of the A side | B side << 16
+    uint32_t hist[FD_NLVL + 2];
     uint32_t off[FD_NLVL + 2];
-    uint32_t cursor[FD_NLVL + 1];
-    int tA[FD_MAXTASKS], tnA[FD_MAXTASKS], tbA[FD_MAXTASKS];
-    int tB[FD_MAXTASKS], tnB[FD_MAXTASKS], tbB[FD_MAXTASKS];
+    uint32_t cur[FD_NLVL + 2];
+    uint32_t eoff[FD_MAXTASKS + 1];  // pair-entry offsets of the workgroup's tasks
+    uint32_t poff[FD_MAXTASKS + 1];  // particle-list offsets of the workgroup's tasks
+    int maxlv;
 };
 
-// Apply all pending pairs level by level, then clear the pending list.
-__device__ void fd_flush(const DevParams &P, FdShared &S, int &npairs, int &maxlvl,
-                         uint32_t step, double dt, FdCount &cnt, bool &negeps)
-{
-    const int lane = threadIdx.x;
-    __syncthreads();
-    if (npairs > 0) {
-        // exclusive prefix over levels 1..64: lane x holds level x + 1
-        const uint32_t h = S.hist[lane + 1];
-        uint32_t incl = h;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t v = (uint32_t)__shfl_up((int)incl, off);
-            if (lane >= off) incl += v;
-        }
-        S.off[lane + 1] = incl - h;
-        S.cursor[lane + 1] = incl - h;
-        __syncthreads();
-        for (int k = lane; k < npairs; k += 64) {
-            const uint32_t pos = atomicAdd(&S.cursor[S.lvl[k]], 1u);
-            S.sorted[pos] = S.pair[k];
-        }
-        __syncthreads();
-        for (int l = 1; l <= maxlvl; ++l) {
-            const int beg = (int)S.off[l], end = beg + (int)S.hist[l];
-            for (int base = beg; base < end; base += 64) {
-                const int k = base + lane;
-                if (k < end) {
-                    const uint32_t pr = S.sorted[k];
-                    int li = (int)(pr & 0xFFFFu), lj = (int)(pr >> 16);
-                    if (S.id[li] > S.id[lj]) {
-                        const int tt = li;
-                        li = lj;
-                        lj = tt;
-                    }
-                    fd_pair(P, step, dt, li, lj, S.q, S.p, S.eps, S.rho, S.id, cnt, negeps);
-                }
-            }
-            __syncthreads();
-        }
-    }
-    S.hist[lane + 1] = 0u;
-    npairs = 0;
-    maxlvl = 0;
-    __syncthreads();
-}
+constexpr uint64_t POS_MASK = (1ull << 25) - 1ull;
 
-__global__ __launch_bounds__(64) void k_fd_phase(DevParams P, FdPhase ph,
+// One launch per phase; one wave per workgroup; the workgroup's tasks are
+// [blockIdx * tpw, +tpw) (tpw <= 64), applied in batches that fit in LDS
+// (normally one).  A batch's particles and pair entries are contiguous in
+// the schedule written by the scheduling pass.
+template <int MAXP, int MAXPAIRS>
+__global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ Pp, FdPhase ph,
                                                  const double *__restrict__ q, double *p,
                                                  double *eps, const double *__restrict__ rho,
                                                  const uint32_t *__restrict__ id,
-                                                 const uint32_t *__restrict__ cell_start,
-                                                 const uint64_t *__restrict__ masks,
+                                                 const uint32_t *__restrict__ pair_off,
+                                                 const uint32_t *__restrict__ part_off,
+                                                 const uint64_t *__restrict__ pairs,
+                                                 const uint32_t *__restrict__ part_list,
+                                                 uint32_t pair_cap, uint32_t part_cap,
                                                  uint32_t step, double dt,
                                                  unsigned long long *counters, uint32_t *err)
 {
-    __shared__ FdShared S;
+    __shared__ FdShared<MAXP, MAXPAIRS> S;
+    constexpr int EPL = MAXPAIRS / 64;   // pair entries per lane in one load pass
+    const DevParams &P = *Pp;
     const int lane = threadIdx.x;
     const int64_t n = P.n;
-    const bool intra = ph.phase == 0;
-    int64_t t = (int64_t)blockIdx.x * ph.tasks_per_wg;
-    const int64_t t_end = t + ph.tasks_per_wg < ph.ntasks ? t + ph.tasks_per_wg : ph.ntasks;
+    const int64_t t0 = (int64_t)blockIdx.x * ph.tasks_per_wg;
+    const int R = (int)(t0 + ph.tasks_per_wg < ph.ntasks ? ph.tasks_per_wg : ph.ntasks - t0);
+    const int64_t T0 = ph.task_base + t0;
     FdCount cnt = {0u, 0u, 0u, 0u, 0u};
-    bool negeps = false, capbad = false;
-    if (lane == 0) S.hist[0] = 0u;
-    S.hist[lane + 1] = 0u;
-    __syncthreads();
+    bool negeps = false;
 
-    while (t < t_end) {
-        // ---- batch of tasks whose particles fit in LDS (uniform control flow)
-        int nt = 0, np = 0;
-        while (t < t_end && nt < FD_MAXTASKS) {
-            int64_t A, B;
-            if (intra) {
-                A = B = t;
-            } else {
-                const int tx = (int)(t % ph.hx), ty = (int)((t / ph.hx) % ph.hy);
-                const int tz = (int)(t / ((int64_t)ph.hx * ph.hy));
-                const int ax = 2 * tx + ph.par[0], ay = 2 * ty + ph.par[1], az = 2 * tz + ph.par[2];
-                int bx = ax + ph.d[0], by = ay + ph.d[1], bz = az + ph.d[2];
-                bx += bx >= P.nc[0] ? -P.nc[0] : (bx < 0 ? P.nc[0] : 0);
-                by += by >= P.nc[1] ? -P.nc[1] : (by < 0 ? P.nc[1] : 0);
-                bz += bz >= P.nc[2] ? -P.nc[2] : (bz < 0 ? P.nc[2] : 0);
-                A = ax + (int64_t)P.nc[0] * (ay + (int64_t)P.nc[1] * az);
-                B = bx + (int64_t)P.nc[0] * (by + (int64_t)P.nc[1] * bz);
-            }
-            const int sA = (int)cell_start[A], nA = (int)cell_start[A + 1] - sA;
-            const int sB = (int)cell_start[B], nB = (int)cell_start[B + 1] - sB;
-            if (nA > P.cap || nB > P.cap) {   // cell overflow: skip, report
-                capbad = true;
-                ++t;
-                continue;
-            }
-            const int need = intra ? nA : nA + nB;
-            if (np + need > FD_MAXP) break;
-            if (lane == 0) {
-                S.tA[nt] = sA;
-                S.tnA[nt] = nA;
-                S.tbA[nt] = np;
-                S.tB[nt] = sB;
-                S.tnB[nt] = nB;
-                S.tbB[nt] = intra ? np : np + nA;
-            }
-            np += need;
-            ++nt;
-            ++t;
+    // offsets of the range's tasks (R + 1 values) and of the phase
+    if (lane < R) {
+        S.eoff[lane] = pair_off[T0 + lane];
+        S.poff[lane] = part_off[T0 + lane];
+    }
+    if (lane == 0) {   // end of the range (R may be 64)
+        S.eoff[R] = pair_off[T0 + R];
+        S.poff[R] = part_off[T0 + R];
+    }
+    const uint32_t phase_p0 = part_off[ph.task_base];
+    __syncthreads();
+    if (S.eoff[R] > pair_cap || S.poff[R] > part_cap) {   // schedule incomplete
+        if (lane == 0) atomicOr(err, ERR_PAIRCAP);
+        return;
+    }
+
+    int k = 0;
+    while (k < R) {
+        // ---- a batch of consecutive tasks that fits (LDS reads only)
+        const int k0 = k;
+        bool oversized = false;
+        while (k < R) {
+            const int c = (int)(S.eoff[k + 1] - S.eoff[k]);
+            const int np_new = (int)(S.poff[k + 1] - S.poff[k0]);
+            const int npr_new = (int)(S.eoff[k + 1] - S.eoff[k0]);
+            if (k > k0 && c > 0 && (np_new > MAXP || npr_new > MAXPAIRS)) break;
+            oversized = c > MAXPAIRS;   // only possible as the first task of a batch
+            ++k;
+            if (oversized) break;
         }
-        __syncthreads();
-        // ---- stage particles
-        for (int k = 0; k < nt; ++k) {
-            const int cells = intra ? 1 : 2;
-            for (int h = 0; h < cells; ++h) {
-                const int g0 = h ? S.tB[k] : S.tA[k];
-                const int cnt_h = h ? S.tnB[k] : S.tnA[k];
-                const int b0 = h ? S.tbB[k] : S.tbA[k];
-                if (lane < cnt_h) {
-                    const int g = g0 + lane, l = b0 + lane;
-                    S.q[0][l] = q[g];
-                    S.q[1][l] = q[n + g];
-                    S.q[2][l] = q[2 * n + g];
-                    S.p[0][l] = p[g];
-                    S.p[1][l] = p[n + g];
-                    S.p[2][l] = p[2 * n + g];
-                    S.eps[l] = eps[g];
-                    S.rho[l] = rho[g];
-                    S.id[l] = id[g];
-                    S.gidx[l] = (uint32_t)g;
+        const uint32_t e_begin = S.eoff[k0], p_begin = S.poff[k0];
+        const int npr = (int)(S.eoff[k] - e_begin), np = (int)(S.poff[k] - p_begin);
+        if (npr == 0) continue;
+        const uint32_t rel0 = p_begin - phase_p0;   // list position of batch particle 0
+        // ---- stage the particles that take part in a pair
+        for (int l = lane; l < np; l += 64) {
+            const int64_t g = part_list[p_begin + l];
+            S.gidx[l] = (uint32_t)g;
+            S.q[0][l] = q[g];
+            S.q[1][l] = q[n + g];
+            S.q[2][l] = q[2 * n + g];
+            S.p[0][l] = p[g];
+            S.p[1][l] = p[n + g];
+            S.p[2][l] = p[2 * n + g];
+            S.eps[l] = eps[g];
+            S.rho[l] = rho[g];
+            S.id[l] = id[g];
+        }
+        // ---- windows of levels (one window unless a single task overflows
+        //      the LDS pair list; then consecutive level ranges that fit)
+        int lo = 1;
+        while (lo <= FD_NLVL) {
+            int hi = FD_NLVL;
+            S.hist[lane + 1] = 0u;
+            if (lane == 0) S.maxlv = 0;
+            __syncthreads();
+            if (oversized) {
+                for (int e = lane; e < npr; e += 64) {
+                    const int lv = (int)(pairs[e_begin + e] >> 50);
+                    if (lv >= 1 && lv <= FD_NLVL) atomicAdd(&S.hist[lv], 1u);
+                }
+                __syncthreads();
+                int acc = 0;
+                for (hi = lo; hi <= FD_NLVL; ++hi) {
+                    if (acc + (int)S.hist[hi] > MAXPAIRS) break;
+                    acc += (int)S.hist[hi];
+                }
+                --hi;
+                hi = hi < lo ? lo : hi;   // one level (<= 64 pairs) always fits
+                __syncthreads();
+                S.hist[lane + 1] = 0u;
+                __syncthreads();
+            }
+            // counting sort of the batch's entries by level: histogram pass,
+            // prefix, scatter pass.  Entries stay in registers (EPL per lane)
+            // between the passes unless the batch needs several load passes.
+            uint64_t ebuf[EPL];
+            const bool one_pass = npr <= MAXPAIRS;
+            for (int base = 0; base < npr; base += MAXPAIRS) {
+#pragma unroll
+                for (int r = 0; r < EPL; ++r) {
+                    const int x = base + r * 64 + lane;
+                    ebuf[r] = x < npr ? pairs[e_begin + x] : 0ull;
+                }
+#pragma unroll
+                for (int r = 0; r < EPL; ++r) {
+                    const int lv = (int)(ebuf[r] >> 50);
+                    if (lv >= lo && lv <= hi && lv <= FD_NLVL) atomicAdd(&S.hist[lv], 1u);
                 }
             }
-        }
-        __syncthreads();
-        // ---- levels of every task, flushing when the pending list is full
-        int npairs = 0, maxlvl = 0;
-        for (int k = 0; k < nt; ++k) {
-            const int nA = S.tnA[k], bA = S.tbA[k], bB = S.tbB[k];
-            const uint64_t mask = lane < nA ? masks[(int64_t)ph.mslot * n + S.tA[k] + lane] : 0ull;
-            const uint64_t rm = xor_permute_bits(mask, (uint32_t)lane);
-            uint64_t rounds = wave_or64(rm);
-            int LA = 0, LB = 0, rcount = 0;
-            while (rounds) {
-                const int s = __builtin_ctzll(rounds);
-                rounds &= rounds - 1;
-                const int partner = lane ^ s;
-                const bool actA = (rm >> s) & 1ull;
-                int la = __shfl(LA, partner), lb = __shfl(LB, partner);
-                const bool actB = __shfl((int)actA, partner) != 0;
-                const bool own = intra ? (actA && lane < partner) : actA;
-                const uint64_t bal = __ballot(own);
-                const int c = __popcll(bal);
-                if (npairs + c > FD_MAXPAIRS) {
-                    fd_flush(P, S, npairs, maxlvl, step, dt, cnt, negeps);
-                    LA = LB = 0;
-                    la = lb = 0;
-                    rcount = 0;
+            __syncthreads();
+            {   // exclusive prefix over levels: lane x holds level x + 1
+                const uint32_t h = S.hist[lane + 1];
+                uint32_t incl = h;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint32_t v = (uint32_t)__shfl_up((int)incl, off);
+                    if (lane >= off) incl += v;
                 }
-                ++rcount;
-                int lvl = 0;
-                if (intra) {
-                    if (actA) LA = (LA > la ? LA : la) + 1;
-                    lvl = LA;
-                } else {
-                    if (actA) LA = (LA > lb ? LA : lb) + 1;
-                    if (actB) LB = (LB > la ? LB : la) + 1;
-                    lvl = LA;
-                }
-                if (own) {
-                    const int pos = npairs + __popcll(bal & ((1ull << lane) - 1ull));
-                    S.pair[pos] = (uint32_t)(bA + lane) | ((uint32_t)(bB + partner) << 16);
-                    S.lvl[pos] = (uint8_t)lvl;
-                    atomicAdd(&S.hist[lvl], 1u);
-                }
-                npairs += c;
-                maxlvl = maxlvl > rcount ? maxlvl : rcount;
+                S.off[lane + 1] = incl - h;
+                S.cur[lane + 1] = incl - h;
+                const uint64_t nz = __ballot(h != 0u);
+                if (lane == 0) S.maxlv = nz ? 64 - __clzll(nz) : 0;
             }
+            __syncthreads();
+            for (int base = 0; base < npr; base += MAXPAIRS) {
+                if (!one_pass) {
+#pragma unroll
+                    for (int r = 0; r < EPL; ++r) {
+                        const int x = base + r * 64 + lane;
+                        ebuf[r] = x < npr ? pairs[e_begin + x] : 0ull;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < EPL; ++r) {
+                    const uint64_t e = ebuf[r];
+                    const int lv = (int)(e >> 50);
+                    const int li = (int)((uint32_t)(e & POS_MASK) - rel0);
+                    const int lj = (int)((uint32_t)((e >> 25) & POS_MASK) - rel0);
+                    if (lv >= lo && lv <= hi && lv <= FD_NLVL && li >= 0 && li < np && lj >= 0 &&
+                        lj < np) {
+                        const uint32_t pos = atomicAdd(&S.cur[lv], 1u);
+                        if (pos < (uint32_t)MAXPAIRS) S.sorted[pos] = (uint32_t)li | ((uint32_t)lj << 16);
+                    }
+                }
+            }
+            __syncthreads();
+            const int top = S.maxlv;
+            for (int l = lo; l <= top; ++l) {
+                const int beg = (int)S.off[l], end = beg + (int)S.hist[l];
+                for (int b0 = beg; b0 < end; b0 += 64) {
+                    const int e = b0 + lane;
+                    if (e < end) {
+                        const uint32_t pr = S.sorted[e];
+                        int li = (int)(pr & 0xFFFFu), lj = (int)(pr >> 16);
+                        if (S.id[li] > S.id[lj]) {
+                            const int tt = li;
+                            li = lj;
+                            lj = tt;
+                        }
+                        fd_pair<MAXP>(P, step, dt, li, lj, S.q, S.p, S.eps, S.rho, S.id, cnt,
+                                      negeps);
+                    }
+                }
+                __syncthreads();
+            }
+            lo = hi + 1;
+            if (!oversized) break;
         }
-        fd_flush(P, S, npairs, maxlvl, step, dt, cnt, negeps);
         // ---- write back momenta and energies
-        for (int k = 0; k < nt; ++k) {
-            const int cells = intra ? 1 : 2;
-            for (int h = 0; h < cells; ++h) {
-                const int cnt_h = h ? S.tnB[k] : S.tnA[k];
-                const int b0 = h ? S.tbB[k] : S.tbA[k];
-                if (lane < cnt_h) {
-                    const int l = b0 + lane, g = (int)S.gidx[l];
-                    p[g] = S.p[0][l];
-                    p[n + g] = S.p[1][l];
-                    p[2 * n + g] = S.p[2][l];
-                    eps[g] = S.eps[l];
-                }
-            }
+        for (int l = lane; l < np; l += 64) {
+            const int64_t g = S.gidx[l];
+            p[g] = S.p[0][l];
+            p[n + g] = S.p[1][l];
+            p[2 * n + g] = S.p[2][l];
+            eps[g] = S.eps[l];
         }
         __syncthreads();
     }
@@ -473,13 +255,20 @@ __global__ __launch_bounds__(64) void k_fd_phase(DevParams P, FdPhase ph,
         if (v3) atomicAdd(&counters[CNT_MARGINAL], (unsigned long long)v3);
         if (v4) atomicAdd(&counters[CNT_NEGEPS], (unsigned long long)v4);
         if (any_neg) atomicOr(err, ERR_NEGEPS);
-        if (capbad) atomicOr(err, ERR_CELLCAP);
     }
 }
+
+// LDS sizes.  Phase 0: ~17 particles and ~150 pairs per cell, so about seven
+// cells fill a batch; inter-cell phases: up to 2 x 64 particles per task and
+// fewer pairs.  Any single task fits the particle arrays (<= 128).
+constexpr int FD_INTRA_P = 192, FD_INTRA_PAIRS = 2048;
+constexpr int FD_INTER_P = 384, FD_INTER_PAIRS = 1536;
 
 int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, uint64_t step, double dt_fd)
 {
     if (c->prm.fd == SDPD_FD_NONE || c->n == 0) return SDPD_OK;
+    int rc = run_schedule(c);
+    if (rc) return rc;
     const int *nc = c->dp.nc;
     for (int phase = 0; phase <= 104; ++phase) {
         FdPhase ph;
@@ -490,7 +279,8 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, uint64_t step, double dt_fd)
             ph.par[0] = ph.par[1] = ph.par[2] = 0;
             ph.hx = ph.hy = 0;
             ph.ntasks = c->ncell;
-            ph.tasks_per_wg = c->fd_tasks_intra;
+            ph.tasks_per_wg = c->fd_tasks[0];
+            ph.task_base = 0;
         } else {
             const int o = (phase - 1) / 8, pi = (phase - 1) % 8, k = 14 + o;
             ph.mslot = o + 1;
@@ -503,16 +293,26 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, uint64_t step, double dt_fd)
             ph.hx = nc[0] / 2;
             ph.hy = nc[1] / 2;
             ph.ntasks = c->ncell / 8;
-            ph.tasks_per_wg = c->fd_tasks_inter;
+            const int cls = (ph.d[0] != 0) + (ph.d[1] != 0) + (ph.d[2] != 0);   // 1, 2, 3
+            ph.tasks_per_wg = c->fd_tasks[cls];
+            ph.task_base = c->ncell + (int64_t)(phase - 1) * (c->ncell / 8);
         }
         const int64_t grid = (ph.ntasks + ph.tasks_per_wg - 1) / ph.tasks_per_wg;
         timer_begin(c, TK_FD);
-        hipLaunchKernelGGL(k_fd_phase, dim3((unsigned)grid), dim3(64), 0, c->stream, c->dp, ph,
-                           s->q, s->p, s->eps, s->rho, s->id, c->cell_start, c->masks,
-                           (uint32_t)step, dt_fd, c->counters, c->err);
+        if (phase == 0)
+            hipLaunchKernelGGL((k_fd_phase<FD_INTRA_P, FD_INTRA_PAIRS>), dim3((unsigned)grid),
+                               dim3(64), 0, c->stream, c->dparams, ph, s->q, s->p, s->eps, s->rho,
+                               s->id, c->pair_off, c->part_off, c->pairs, c->part_list,
+                               (uint32_t)c->pair_cap, (uint32_t)c->part_cap, (uint32_t)step,
+                               dt_fd, c->counters, c->err);
+        else
+            hipLaunchKernelGGL((k_fd_phase<FD_INTER_P, FD_INTER_PAIRS>), dim3((unsigned)grid),
+                               dim3(64), 0, c->stream, c->dparams, ph, s->q, s->p, s->eps, s->rho,
+                               s->id, c->pair_off, c->part_off, c->pairs, c->part_list,
+                               (uint32_t)c->pair_cap, (uint32_t)c->part_cap, (uint32_t)step,
+                               dt_fd, c->counters, c->err);
         timer_end(c, TK_FD);
-        int rc = check_hip(hipGetLastError());
-        if (rc) return rc;
+        if ((rc = check_hip(hipGetLastError()))) return rc;
     }
     return SDPD_OK;
 }

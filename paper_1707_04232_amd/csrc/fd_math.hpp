@@ -1,0 +1,223 @@
+// Device math of one fluctuation/dissipation pair update (Sec. 3.2-3.3 of
+// Faure & Stoltz): Philox4x32-10 draws, the Ornstein-Uhlenbeck proposal in
+// the relative velocity, the energy bound and the Metropolis log-ratio.
+#pragma once
+
+#include "sdpd_internal.hpp"
+
+namespace sdpd {
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 32x32->64 products with multipliers 0xD2511F53 and 0xCD9E8D57, key
+// advanced by the Weyl constants 0x9E3779B9 and 0xBB67AE85 between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t &x0, uint32_t &x1, uint32_t &x2,
+                                              uint32_t &x3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)0xD2511F53u * x0;
+        const uint64_t b = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t y0 = (uint32_t)(b >> 32) ^ x1 ^ k0;
+        const uint32_t y2 = (uint32_t)(a >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)b;
+        x3 = (uint32_t)a;
+        x0 = y0;
+        x2 = y2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+__device__ __forceinline__ double open_unit(uint32_t w)
+{
+    return ((double)w + 0.5) * 2.3283064365386962890625e-10;  // (w + 1/2) 2^-32
+}
+
+// Gaussian vector (Box-Muller on the first block) and uniform of one pair
+__device__ __forceinline__ void pair_draws(const DevParams &P, uint32_t step, uint32_t id_i,
+                                           uint32_t id_j, double G[3], double &U)
+{
+    uint32_t a0 = step, a1 = id_i, a2 = id_j, a3 = P.replica * 2u;
+    uint32_t b0 = step, b1 = id_i, b2 = id_j, b3 = P.replica * 2u + 1u;
+    philox4x32_10(a0, a1, a2, a3, P.seed_lo, P.seed_hi);
+    philox4x32_10(b0, b1, b2, b3, P.seed_lo, P.seed_hi);
+    const double R1 = sqrt(-2.0 * log(open_unit(a0)));
+    const double R2 = sqrt(-2.0 * log(open_unit(a2)));
+    double s1, c1;
+    sincospi(2.0 * open_unit(a1), &s1, &c1);
+    G[0] = R1 * c1;
+    G[1] = R1 * s1;
+    G[2] = R2 * cospi(2.0 * open_unit(a3));
+    U = open_unit(b0);
+}
+
+// ---------------------------------------------------------------- coefficients
+// alpha^theta and the squared relative-velocity noise amplitude
+// b^theta^2 = ((2/m) zeta^theta)^2 at energies (ei, ej).  With
+// gamma = kappa (1 - d) and sigma^2 = 4 kappa kB T_i T_j/(T_i + T_j) of
+// eq. (sdpd-gamma-sigma), zeta^2 = sigma^2 m (1 - alpha^2)/(4 gamma) reduces
+// to m kB T_red (1 - alpha^2)/(1 - d) with T_red = T_i T_j/(T_i + T_j), so
+// b^2 = (4 kB/m) T_red (1 - alpha^2)/(1 - d).  With e = expm1(-2 gamma dt/m):
+// alpha = 1 + e and 1 - alpha^2 = -e (2 + e), both without cancellation.
+struct Coef {
+    double al_par, al_perp, b2_par, b2_perp;
+};
+
+__device__ __forceinline__ Coef fd_coef(const DevParams &P, double kpar, double kperp, double ei,
+                                        double ej, double dt)
+{
+    const double Ti = ei * P.inv_Cv, Tj = ej * P.inv_Cv;
+    const double inv_Ts = 1.0 / (Ti + Tj);
+    const double Tred = Ti * Tj * inv_Ts;
+    const double d = P.kB * Tred * inv_Ts * P.two_over_Cv;
+    const double omd = 1.0 - d;
+    const double c = -2.0 * dt * P.inv_m * omd;
+    const double e_par = expm1(c * kpar), e_perp = expm1(c * kperp);
+    const double s = P.b2_c * Tred / omd;
+    Coef r;
+    r.al_par = 1.0 + e_par;
+    r.al_perp = 1.0 + e_perp;
+    r.b2_par = -s * e_par * (2.0 + e_par);
+    r.b2_perp = -s * e_perp * (2.0 + e_perp);
+    return r;
+}
+
+struct FdCount {
+    uint32_t proposed, rej_energy, rej_ratio, marginal, negeps;
+};
+
+// One pair update on LDS-resident state; li has the smaller id.  s_q and s_p
+// hold the x, y, z planes at stride MAXP.
+template <int MAXP>
+__device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, double dt, int li,
+                                        int lj, double (*s_q)[MAXP], double (*s_p)[MAXP],
+                                        double *s_eps, const double *s_rho,
+                                        const uint32_t *s_id, FdCount &cnt, bool &negeps)
+{
+    // geometry (Sec. 2.1.1): r_ij, e_ij, F_ij
+    const double dx = min_image(s_q[0][li] - s_q[0][lj], P.box[0], P.half_box[0]);
+    const double dy = min_image(s_q[1][li] - s_q[1][lj], P.box[1], P.half_box[1]);
+    const double dz = min_image(s_q[2][li] - s_q[2][lj], P.box[2], P.half_box[2]);
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const double inv_r = 1.0 / r;
+    const double ex = dx * inv_r, ey = dy * inv_r, ez = dz * inv_r;
+    const double x = r * P.inv_h, t = 1.0 - x;
+    double F;
+    if (P.kernel == SDPD_KERNEL_LUCY) F = P.cF * (t * t);
+    else F = x <= 0.5 ? P.cF * (2.0 - 3.0 * x) : P.cF * P.h * (t * t) * inv_r;
+    // kappa^theta of Sec. 2.2.2
+    const double kfac = F / (s_rho[li] * s_rho[lj]);
+    const double kpar = P.kpar_c * kfac, kperp = P.kperp_c * kfac;
+
+    const double ei = s_eps[li], ej = s_eps[lj];
+    const double vx = (s_p[0][li] - s_p[0][lj]) * P.inv_m;
+    const double vy = (s_p[1][li] - s_p[1][lj]) * P.inv_m;
+    const double vz = (s_p[2][li] - s_p[2][lj]) * P.inv_m;
+
+    double G[3], U;
+    pair_draws(P, step, s_id[li], s_id[lj], G, U);
+
+    // proposal, eq. (proposal): v' = A(v) v + B(v) G, B = (2/m) zeta^theta P^theta
+    const Coef f = fd_coef(P, kpar, kperp, ei, ej, dt);
+    const double b_par = sqrt(f.b2_par), b_perp = sqrt(f.b2_perp);
+    const double vpar = vx * ex + vy * ey + vz * ez;
+    const double Gpar = G[0] * ex + G[1] * ey + G[2] * ez;
+    const double vqx = vx - vpar * ex, vqy = vy - vpar * ey, vqz = vz - vpar * ez;
+    const double Gqx = G[0] - Gpar * ex, Gqy = G[1] - Gpar * ey, Gqz = G[2] - Gpar * ez;
+    const double npar = f.al_par * vpar + b_par * Gpar;
+    const double nqx = f.al_perp * vqx + b_perp * Gqx;
+    const double nqy = f.al_perp * vqy + b_perp * Gqy;
+    const double nqz = f.al_perp * vqz + b_perp * Gqz;
+    const double nvx = npar * ex + nqx, nvy = npar * ey + nqy, nvz = npar * ez + nqz;
+    // energy change, eq. (proposal-update)
+    const double delta = P.m_over_8 * ((nvx * nvx + nvy * nvy + nvz * nvz)
+                                       - (vx * vx + vy * vy + vz * vz));
+    const double emin = fmin(ei, ej);
+    bool accept = true;
+    cnt.proposed += 1;
+    if (P.fd == SDPD_FD_SSA) {
+        if (!(ei - delta > 0.0 && ej - delta > 0.0)) {
+            cnt.negeps += 1;
+            negeps = true;
+        }
+    } else {
+        if (fabs(emin - delta) <= 1e-12 * fmax(fabs(emin), fabs(delta))) cnt.marginal += 1;
+        if (!(emin > delta)) {                       // eq. (energy-bound)
+            accept = false;
+            cnt.rej_energy += 1;
+        } else if (P.fd == SDPD_FD_EMS) {
+            // reverse move from v' at the proposed energies, eq. (metropolis-ratio)
+            const double ei2 = ei - delta, ej2 = ej - delta;
+            const Coef g = fd_coef(P, kpar, kperp, ei2, ej2, dt);
+            const double wpar = vpar - g.al_par * npar;
+            const double wqx = vqx - g.al_perp * nqx;
+            const double wqy = vqy - g.al_perp * nqy;
+            const double wqz = vqz - g.al_perp * nqz;
+            const double quad = wpar * wpar / g.b2_par + (wqx * wqx + wqy * wqy + wqz * wqz) / g.b2_perp;
+            const double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+            // log|B(v)| - log|B(v')| = (1/2) log(b_par^2 b_perp^4 / (b'_par^2 b'_perp^4))
+            const double logdet = 0.5 * log((f.b2_par * f.b2_perp * f.b2_perp)
+                                            / (g.b2_par * g.b2_perp * g.b2_perp));
+            // ideal gas: sum_k (S(eps'_k) - S(eps_k))/kB - log T(eps'_k) + log T(eps_k)
+            //          = (Cv/kB - 1) log((1 - delta/ei)(1 - delta/ej))
+            const double ui = -delta / ei, uj = -delta / ej;
+            const double ent = P.ent_c * log1p(ui + uj + ui * uj);
+            const double a = 0.5 * G2 - 0.5 * quad + logdet + ent;
+            const double lnU = log(U);
+            if (fabs(a - lnU) <= 1e-9) cnt.marginal += 1;
+            if (!(lnU <= a)) {                       // reject iff U > exp(a)
+                accept = false;
+                cnt.rej_ratio += 1;
+            }
+        }
+    }
+    if (accept) {
+        const double hm = P.m_over_2;
+        const double dpx = hm * (nvx - vx), dpy = hm * (nvy - vy), dpz = hm * (nvz - vz);
+        s_p[0][li] += dpx;
+        s_p[1][li] += dpy;
+        s_p[2][li] += dpz;
+        s_p[0][lj] -= dpx;
+        s_p[1][lj] -= dpy;
+        s_p[2][lj] -= dpz;
+        s_eps[li] = ei - delta;
+        s_eps[lj] = ej - delta;
+    }
+}
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ uint64_t xor_permute_bits(uint64_t m, uint32_t x)
+{
+    // bit b of m moves to bit b ^ x
+    const uint64_t M[6] = {0x5555555555555555ull, 0x3333333333333333ull,
+                           0x0F0F0F0F0F0F0F0Full, 0x00FF00FF00FF00FFull,
+                           0x0000FFFF0000FFFFull, 0x00000000FFFFFFFFull};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int sh = 1 << k;
+        const uint64_t sw = ((m & M[k]) << sh) | ((m >> sh) & M[k]);
+        m = ((x >> k) & 1u) ? sw : m;
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v)
+{
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo |= (uint32_t)__shfl_xor((int)lo, off);
+        hi |= (uint32_t)__shfl_xor((int)hi, off);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off);
+    return v;
+}
+
+}  // namespace sdpd

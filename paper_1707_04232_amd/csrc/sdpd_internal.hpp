@@ -11,7 +11,7 @@
 namespace sdpd {
 
 // sticky device error bits
-enum : uint32_t { ERR_CELLCAP = 1u, ERR_NEGEPS = 2u, ERR_NONFINITE = 4u };
+enum : uint32_t { ERR_CELLCAP = 1u, ERR_NEGEPS = 2u, ERR_NONFINITE = 4u, ERR_PAIRCAP = 8u };
 
 // F/D counters, in this order in the device counter array
 enum { CNT_PROPOSED = 0, CNT_REJ_ENERGY, CNT_REJ_RATIO, CNT_MARGINAL, CNT_NEGEPS, CNT_N };
@@ -62,6 +62,7 @@ struct Timer {
 struct sdpd_ctx {
     sdpd_params prm;
     sdpd::DevParams dp;
+    sdpd::DevParams *dparams;    // device copy of dp (read by kernels through a pointer)
     hipStream_t stream;
     int device;
     int64_t n, ncell;
@@ -80,7 +81,11 @@ struct sdpd_ctx {
     double *obs_out;             // device stats records
     int64_t obs_cap;
     int cells_valid, masks_valid;
-    int fd_tasks_intra, fd_tasks_inter;   // tasks per workgroup of the F/D kernel
+    int fd_tasks[4];             // tasks per F/D workgroup: own cell, face, edge, corner phases
+    // pair schedule (rebuilt before every sweep)
+    uint32_t *task_count, *task_np, *pair_off, *part_off, *part_list;
+    uint64_t *pairs;
+    int64_t pair_cap, part_cap;
     sdpd::Timer timer;
     int timing;
     double last_fd_ms;
@@ -94,6 +99,9 @@ int check_hip(hipError_t e);
 // host launchers (each returns an sdpd_status)
 int launch_fill_u32(sdpd_ctx *c, uint32_t *p, uint32_t v, int64_t n);
 int launch_fill_u64(sdpd_ctx *c, unsigned long long *p, unsigned long long v, int64_t n);
+int run_scan(sdpd_ctx *c, const uint32_t *in, uint32_t *out, int64_t count, uint32_t *block_sums,
+             int cap);
+int run_schedule(sdpd_ctx *c);
 int run_build_cells(sdpd_ctx *c, const sdpd_state *s, int kick_drift);
 int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps);
 int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick);

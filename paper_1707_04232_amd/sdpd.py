@@ -13,7 +13,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsdpd.so")
 
-OK, EINVAL, EHIP, ENOMEM, ECELLCAP, ENEGEPS, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, EHIP, ENOMEM, ECELLCAP, ENEGEPS, ENONFINITE, ECAPACITY = 0, -1, -2, -3, -4, -5, -6, -7
 KERNEL_LUCY, KERNEL_CUBIC = 0, 1
 FD_EMS, FD_AMS, FD_SSA, FD_NONE = 0, 1, 2, 3
 TIMING_CLASSES = ("cells", "density", "fd", "forces", "observe")
@@ -79,7 +79,7 @@ def lib():
             "sdpd_sync": [vp],
             "sdpd_set_timing": [vp, i32],
             "sdpd_timing": [vp, C.POINTER(C.c_double), C.POINTER(i64)],
-            "sdpd_tune": [vp, i32, i32],
+            "sdpd_tune": [vp, C.POINTER(C.c_int32)],
             "sdpd_abi_version": [],
         }
         for name, args in sig.items():
@@ -250,8 +250,10 @@ class Context:
         _check(lib().sdpd_timing(self._h, ms, cnt), "sdpd_timing")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(TIMING_CLASSES)}
 
-    def tune(self, fd_tasks_intra: int, fd_tasks_inter: int):
-        _check(lib().sdpd_tune(self._h, int(fd_tasks_intra), int(fd_tasks_inter)), "sdpd_tune")
+    def tune(self, fd_tasks):
+        """tasks per F/D workgroup: (own cell, face, edge, corner) phases."""
+        arr = (C.c_int32 * 4)(*[int(x) for x in fd_tasks])
+        _check(lib().sdpd_tune(self._h, arr), "sdpd_tune")
 
     def prepare(self, s: DeviceState):
         """cells, density without energy update, forces: the entry state of step()."""

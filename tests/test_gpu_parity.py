@@ -149,10 +149,10 @@ def test_fd_sweep_parity(name, dims, Cv, T, dt, mode, kernel, zeta):
 def test_fd_sweep_tuning_does_not_change_results():
     say("fd sweep tuning invariance")
     outs = []
-    for tasks in ((16, 8), (1, 1), (3, 5), (64, 64)):
+    for tasks in ((9, 12, 16, 26), (1, 1, 1, 1), (3, 5, 2, 7), (64, 64, 64, 64)):
         gp, op, S, R = _fd_case((24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0)
         with sd().Context(gp) as ctx:
-            ctx.tune(*tasks)
+            ctx.tune(tasks)
             ctx.prepare(S)
             ctx.fd_metropolis(S, step=3)
         outs.append(S.to_numpy())
