@@ -121,6 +121,7 @@ static void derive(const sdpd_params *P, const int nc[3], DevParams &d)
     d.ent_c = P->Cv / P->kB - 1.0;
     d.m_over_8 = P->m / 8.0;
     d.m_over_2 = P->m / 2.0;
+    d.par_twice_perp = d.kpar_c == 2.0 * d.kperp_c;
 }
 
 template <typename T>

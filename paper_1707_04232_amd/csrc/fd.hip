@@ -118,19 +118,33 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
         const int npr = (int)(S.eoff[k] - e_begin), np = (int)(S.poff[k] - p_begin);
         if (npr == 0) continue;
         const uint32_t rel0 = p_begin - phase_p0;   // list position of batch particle 0
-        // ---- stage the particles that take part in a pair
-        for (int l = lane; l < np; l += 64) {
-            const int64_t g = part_list[p_begin + l];
-            S.gidx[l] = (uint32_t)g;
-            S.q[0][l] = q[g];
-            S.q[1][l] = q[n + g];
-            S.q[2][l] = q[2 * n + g];
-            S.p[0][l] = p[g];
-            S.p[1][l] = p[n + g];
-            S.p[2][l] = p[2 * n + g];
-            S.eps[l] = eps[g];
-            S.rho[l] = rho[g];
-            S.id[l] = id[g];
+        // ---- stage the particles that take part in a pair: list entries
+        //      first (one round-trip), then all state loads
+        {
+            constexpr int PPL = (MAXP + 63) / 64;
+            uint32_t gl[PPL];
+#pragma unroll
+            for (int r = 0; r < PPL; ++r) {
+                const int l = r * 64 + lane;
+                gl[r] = l < np ? part_list[p_begin + l] : 0u;
+            }
+#pragma unroll
+            for (int r = 0; r < PPL; ++r) {
+                const int l = r * 64 + lane;
+                if (l < np) {
+                    const int64_t g = gl[r];
+                    S.gidx[l] = (uint32_t)g;
+                    S.q[0][l] = q[g];
+                    S.q[1][l] = q[n + g];
+                    S.q[2][l] = q[2 * n + g];
+                    S.p[0][l] = p[g];
+                    S.p[1][l] = p[n + g];
+                    S.p[2][l] = p[2 * n + g];
+                    S.eps[l] = eps[g];
+                    S.rho[l] = rho[g];
+                    S.id[l] = id[g];
+                }
+            }
         }
         // ---- windows of levels (one window unless a single task overflows
         //      the LDS pair list; then consecutive level ranges that fit)

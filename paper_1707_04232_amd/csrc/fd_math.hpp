@@ -34,10 +34,32 @@ __device__ __forceinline__ double open_unit(uint32_t w)
     return ((double)w + 0.5) * 2.3283064365386962890625e-10;  // (w + 1/2) 2^-32
 }
 
+// Reciprocal and reciprocal square root to about one ulp: the hardware
+// estimate refined by two Newton steps (the F/D update only needs relative
+// accuracy far below its 1e-10 parity bar; IEEE division costs twice as much).
+__device__ __forceinline__ double fast_rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double fast_rsq(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
 // Gaussian vector (Box-Muller on the first block) and uniform of one pair
 __device__ __forceinline__ void pair_draws(const DevParams &P, uint32_t step, uint32_t id_i,
                                            uint32_t id_j, double G[3], double &U)
 {
+#pragma clang fp contract(fast)
     uint32_t a0 = step, a1 = id_i, a2 = id_j, a3 = P.replica * 2u;
     uint32_t b0 = step, b1 = id_i, b2 = id_j, b3 = P.replica * 2u + 1u;
     philox4x32_10(a0, a1, a2, a3, P.seed_lo, P.seed_hi);
@@ -64,17 +86,21 @@ struct Coef {
     double al_par, al_perp, b2_par, b2_perp;
 };
 
+// When zeta = 0 the parallel friction is exactly twice the perpendicular one,
+// and expm1(2y) = e (2 + e) with e = expm1(y) saves one exponential.
 __device__ __forceinline__ Coef fd_coef(const DevParams &P, double kpar, double kperp, double ei,
                                         double ej, double dt)
 {
+#pragma clang fp contract(fast)
     const double Ti = ei * P.inv_Cv, Tj = ej * P.inv_Cv;
-    const double inv_Ts = 1.0 / (Ti + Tj);
+    const double inv_Ts = fast_rcp(Ti + Tj);
     const double Tred = Ti * Tj * inv_Ts;
     const double d = P.kB * Tred * inv_Ts * P.two_over_Cv;
     const double omd = 1.0 - d;
     const double c = -2.0 * dt * P.inv_m * omd;
-    const double e_par = expm1(c * kpar), e_perp = expm1(c * kperp);
-    const double s = P.b2_c * Tred / omd;
+    const double e_perp = expm1(c * kperp);
+    const double e_par = P.par_twice_perp ? e_perp * (2.0 + e_perp) : expm1(c * kpar);
+    const double s = P.b2_c * Tred * fast_rcp(omd);
     Coef r;
     r.al_par = 1.0 + e_par;
     r.al_perp = 1.0 + e_perp;
@@ -95,19 +121,21 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, doubl
                                         double *s_eps, const double *s_rho,
                                         const uint32_t *s_id, FdCount &cnt, bool &negeps)
 {
+#pragma clang fp contract(fast)
     // geometry (Sec. 2.1.1): r_ij, e_ij, F_ij
     const double dx = min_image(s_q[0][li] - s_q[0][lj], P.box[0], P.half_box[0]);
     const double dy = min_image(s_q[1][li] - s_q[1][lj], P.box[1], P.half_box[1]);
     const double dz = min_image(s_q[2][li] - s_q[2][lj], P.box[2], P.half_box[2]);
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    const double inv_r = 1.0 / r;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double inv_r = fast_rsq(r2);
+    const double r = r2 * inv_r;
     const double ex = dx * inv_r, ey = dy * inv_r, ez = dz * inv_r;
     const double x = r * P.inv_h, t = 1.0 - x;
     double F;
     if (P.kernel == SDPD_KERNEL_LUCY) F = P.cF * (t * t);
     else F = x <= 0.5 ? P.cF * (2.0 - 3.0 * x) : P.cF * P.h * (t * t) * inv_r;
     // kappa^theta of Sec. 2.2.2
-    const double kfac = F / (s_rho[li] * s_rho[lj]);
+    const double kfac = F * fast_rcp(s_rho[li] * s_rho[lj]);
     const double kpar = P.kpar_c * kfac, kperp = P.kperp_c * kfac;
 
     const double ei = s_eps[li], ej = s_eps[lj];
@@ -154,14 +182,16 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, doubl
             const double wqx = vqx - g.al_perp * nqx;
             const double wqy = vqy - g.al_perp * nqy;
             const double wqz = vqz - g.al_perp * nqz;
-            const double quad = wpar * wpar / g.b2_par + (wqx * wqx + wqy * wqy + wqz * wqz) / g.b2_perp;
+            const double quad = wpar * wpar * fast_rcp(g.b2_par)
+                                + (wqx * wqx + wqy * wqy + wqz * wqz) * fast_rcp(g.b2_perp);
             const double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
             // log|B(v)| - log|B(v')| = (1/2) log(b_par^2 b_perp^4 / (b'_par^2 b'_perp^4))
             const double logdet = 0.5 * log((f.b2_par * f.b2_perp * f.b2_perp)
-                                            / (g.b2_par * g.b2_perp * g.b2_perp));
+                                            * fast_rcp(g.b2_par * g.b2_perp * g.b2_perp));
             // ideal gas: sum_k (S(eps'_k) - S(eps_k))/kB - log T(eps'_k) + log T(eps_k)
             //          = (Cv/kB - 1) log((1 - delta/ei)(1 - delta/ej))
-            const double ui = -delta / ei, uj = -delta / ej;
+            const double inv_eiej = fast_rcp(ei * ej);
+            const double ui = -delta * ej * inv_eiej, uj = -delta * ei * inv_eiej;
             const double ent = P.ent_c * log1p(ui + uj + ui * uj);
             const double a = 0.5 * G2 - 0.5 * quad + logdet + ent;
             const double lnU = log(U);

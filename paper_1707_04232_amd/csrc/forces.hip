@@ -125,22 +125,35 @@ __global__ __launch_bounds__(OBS_THREADS) void k_observe_partial(DevParams P, co
 }
 
 
-__global__ void k_observe_final(const double *partial, int64_t nblocks,
-                                const unsigned long long *counters, double *rec)
+// one workgroup: partials summed in a fixed tree order (deterministic)
+__global__ __launch_bounds__(OBS_THREADS) void k_observe_final(const double *partial,
+                                                               int64_t nblocks,
+                                                               const unsigned long long *counters,
+                                                               double *rec)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ double s[OBS_FIELDS][OBS_THREADS];
     double v[OBS_FIELDS] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
-    for (int64_t b = 0; b < nblocks; ++b) {
+    for (int64_t b = threadIdx.x; b < nblocks; b += OBS_THREADS) {
         for (int k = 0; k < 5; ++k) v[k] += partial[b * OBS_FIELDS + k];
         v[5] = fmin(v[5], partial[b * OBS_FIELDS + 5]);
     }
-    rec[0] = v[0] + v[1];
-    rec[1] = v[0];
-    rec[2] = v[1];
-    rec[3] = v[2];
-    rec[4] = v[3];
-    rec[5] = v[4];
-    rec[6] = v[5];
+    for (int k = 0; k < OBS_FIELDS; ++k) s[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int off = OBS_THREADS / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            for (int k = 0; k < 5; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + off];
+            s[5][threadIdx.x] = fmin(s[5][threadIdx.x], s[5][threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    rec[0] = s[0][0] + s[1][0];
+    rec[1] = s[0][0];
+    rec[2] = s[1][0];
+    rec[3] = s[2][0];
+    rec[4] = s[3][0];
+    rec[5] = s[4][0];
+    rec[6] = s[5][0];
     unsigned long long *ci = reinterpret_cast<unsigned long long *>(rec + 7);
     for (int k = 0; k < CNT_N; ++k) ci[k] = counters[k];
 }
@@ -150,7 +163,7 @@ int run_observe(sdpd_ctx *c, const sdpd_state *s, double *dst_record)
     if (c->n > 0)
         hipLaunchKernelGGL(k_observe_partial, dim3((unsigned)c->obs_blocks), dim3(OBS_THREADS), 0,
                            c->stream, c->dp, s->p, s->eps, c->obs_partial);
-    hipLaunchKernelGGL(k_observe_final, dim3(1), dim3(64), 0, c->stream, c->obs_partial,
+    hipLaunchKernelGGL(k_observe_final, dim3(1), dim3(OBS_THREADS), 0, c->stream, c->obs_partial,
                        c->n > 0 ? c->obs_blocks : 0, c->counters, dst_record);
     return check_hip(hipGetLastError());
 }

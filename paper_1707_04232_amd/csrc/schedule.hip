@@ -159,7 +159,8 @@ int run_schedule(sdpd_ctx *c)
     if (rc) return rc;
     if ((rc = run_scan(c, c->task_count, c->pair_off, ntask, c->block_sums, -1))) return rc;
     if ((rc = run_scan(c, c->task_np, c->part_off, ntask, c->block_sums, -1))) return rc;
-    const int64_t grid = std::min<int64_t>(ntask, 65536);
+    // one workgroup per task: many independent short tasks hide the load latency
+    const int64_t grid = std::min<int64_t>(ntask, 0x7fffffffLL);
     hipLaunchKernelGGL(k_schedule, dim3((unsigned)grid), dim3(64), 0, c->stream, c->dparams,
                        c->cell_start, c->masks, c->pair_off, c->part_off, c->pairs, c->part_list,
                        (uint32_t)c->pair_cap, (uint32_t)c->part_cap, c->err);

@@ -42,6 +42,7 @@ struct DevParams {
     double b2_c;        // 4 kB / m
     double ent_c;       // Cv/kB - 1
     double m_over_8, m_over_2;
+    int par_twice_perp;     // kpar_c == 2 kperp_c exactly (zeta = 0)
 };
 
 // observable record (doubles): E, Eint, KE, P0, P1, P2, min_eps, then the
