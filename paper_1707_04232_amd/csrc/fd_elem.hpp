@@ -1,0 +1,121 @@
+// Compact FP64 elementary functions for the fluctuation/dissipation update.
+//
+// Their arguments are always positive, finite and well ranged (uniform draws
+// in (0, 1), energies, ratios of friction amplitudes), so the special-case
+// handling of a general math library is not needed.  Accuracy: a few ulp,
+// far below the 1e-10 agreement required with the FP64 oracle.
+//   * log: x = m 2^e with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(f),
+//     f = (m - 1)/(m + 1), |f| <= 0.1716, atanh series to f^23;
+//     e ln 2 added with a two-part ln 2 (32-bit head, so e * head is exact).
+//   * log1p: log(1 + x) plus the exact rounding error of 1 + x divided by
+//     1 + x (the error is recovered with the Fast2Sum step).
+//   * sin(pi t), cos(pi t): t reduced by multiples of 1/2 to |r| <= 1/4,
+//     Taylor polynomials of sin(pi r) and cos(pi r) to degree 19 / 18, then a
+//     quarter-turn rotation.
+//   * sqrt: reciprocal square root estimate with two Newton steps, one
+//     Newton correction of the product.
+#pragma once
+
+namespace sdpd {
+
+// reciprocal to about one ulp: hardware estimate and two Newton steps
+__device__ __forceinline__ double fast_rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// reciprocal square root to about one ulp
+__device__ __forceinline__ double fast_rsq(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+__device__ __forceinline__ double fd_sqrt(double x)
+{
+    const double y = fast_rsq(x);
+    const double s = x * y;
+    return fma(0.5 * y, fma(-s, s, x), s);
+}
+
+__device__ __forceinline__ double fd_log(double x)
+{
+    int e;
+    double m = frexp(x, &e);   // m in [0.5, 1)
+    const bool low = m < 0.7071067811865476;
+    m = low ? 2.0 * m : m;
+    e = low ? e - 1 : e;
+    const double f = (m - 1.0) * fast_rcp(m + 1.0);
+    const double s = f * f;
+    // 2 atanh(f) = 2 f + f s (2/3 + 2/5 s + 2/7 s^2 + ... + 2/23 s^10)
+    double p = 0.08695652173913043;
+    p = fma(p, s, 0.09523809523809523);
+    p = fma(p, s, 0.10526315789473684);
+    p = fma(p, s, 0.11764705882352941);
+    p = fma(p, s, 0.13333333333333333);
+    p = fma(p, s, 0.15384615384615385);
+    p = fma(p, s, 0.18181818181818182);
+    p = fma(p, s, 0.2222222222222222);
+    p = fma(p, s, 0.2857142857142857);
+    p = fma(p, s, 0.4);
+    p = fma(p, s, 0.6666666666666666);
+    const double lm = fma(f * s, p, 2.0 * f);
+    const double de = (double)e;
+    return fma(de, 0.6931471803691238, fma(de, 1.9082149292705877e-10, lm));
+}
+
+// log(1 + x) for x > -1
+__device__ __forceinline__ double fd_log1p(double x)
+{
+    const double y = 1.0 + x;
+    const double c = fabs(x) < 1.0 ? x - (y - 1.0) : 1.0 - (y - x);
+    return fd_log(y) + c * fast_rcp(y);
+}
+
+__device__ __forceinline__ void fd_sincospi_reduced(double r, double &s, double &c)
+{
+    const double z = r * r;
+    double ps = -2.2948428997269873e-08;
+    ps = fma(ps, z, 7.952054001475513e-07);
+    ps = fma(ps, z, -2.1915353447830217e-05);
+    ps = fma(ps, z, 0.00046630280576761255);
+    ps = fma(ps, z, -0.0073704309457143504);
+    ps = fma(ps, z, 0.08214588661112823);
+    ps = fma(ps, z, -0.5992645293207921);
+    ps = fma(ps, z, 2.5501640398773455);
+    ps = fma(ps, z, -5.16771278004997);
+    ps = fma(ps, z, 3.141592653589793);
+    double pc = -1.3878952462213771e-07;
+    pc = fma(pc, z, 4.303069587032947e-06);
+    pc = fma(pc, z, -0.0001046381049248457);
+    pc = fma(pc, z, 0.0019295743094039231);
+    pc = fma(pc, z, -0.02580689139001406);
+    pc = fma(pc, z, 0.2353306303588932);
+    pc = fma(pc, z, -1.3352627688545895);
+    pc = fma(pc, z, 4.0587121264167685);
+    pc = fma(pc, z, -4.934802200544679);
+    pc = fma(pc, z, 1.0);
+    s = r * ps;
+    c = pc;
+}
+
+// sin(pi t), cos(pi t) for 0 <= t <= 2
+__device__ __forceinline__ void fd_sincospi(double t, double &s, double &c)
+{
+    const double k = rint(2.0 * t);   // quarter turns, 0..4
+    const double r = t - 0.5 * k;     // exact, |r| <= 1/4
+    double sr, cr;
+    fd_sincospi_reduced(r, sr, cr);
+    const int q = ((int)k) & 3;
+    s = q == 0 ? sr : (q == 1 ? cr : (q == 2 ? -sr : -cr));
+    c = q == 0 ? cr : (q == 1 ? -sr : (q == 2 ? -cr : sr));
+}
+
+}  // namespace sdpd

@@ -4,6 +4,7 @@
 #pragma once
 
 #include "sdpd_internal.hpp"
+#include "fd_elem.hpp"
 
 namespace sdpd {
 
@@ -34,27 +35,6 @@ __device__ __forceinline__ double open_unit(uint32_t w)
     return ((double)w + 0.5) * 2.3283064365386962890625e-10;  // (w + 1/2) 2^-32
 }
 
-// Reciprocal and reciprocal square root to about one ulp: the hardware
-// estimate refined by two Newton steps (the F/D update only needs relative
-// accuracy far below its 1e-10 parity bar; IEEE division costs twice as much).
-__device__ __forceinline__ double fast_rcp(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-
-__device__ __forceinline__ double fast_rsq(double x)
-{
-    double y = __builtin_amdgcn_rsq(x);
-    double h = 0.5 * x;
-    y = y * fma(-h * y, y, 1.5);
-    y = y * fma(-h * y, y, 1.5);
-    return y;
-}
-
 // Gaussian vector (Box-Muller on the first block) and uniform of one pair
 __device__ __forceinline__ void pair_draws(const DevParams &P, uint32_t step, uint32_t id_i,
                                            uint32_t id_j, double G[3], double &U)
@@ -64,13 +44,14 @@ __device__ __forceinline__ void pair_draws(const DevParams &P, uint32_t step, ui
     uint32_t b0 = step, b1 = id_i, b2 = id_j, b3 = P.replica * 2u + 1u;
     philox4x32_10(a0, a1, a2, a3, P.seed_lo, P.seed_hi);
     philox4x32_10(b0, b1, b2, b3, P.seed_lo, P.seed_hi);
-    const double R1 = sqrt(-2.0 * log(open_unit(a0)));
-    const double R2 = sqrt(-2.0 * log(open_unit(a2)));
-    double s1, c1;
-    sincospi(2.0 * open_unit(a1), &s1, &c1);
+    const double R1 = fd_sqrt(-2.0 * fd_log(open_unit(a0)));
+    const double R2 = fd_sqrt(-2.0 * fd_log(open_unit(a2)));
+    double s1, c1, s3, c3;
+    fd_sincospi(2.0 * open_unit(a1), s1, c1);
+    fd_sincospi(2.0 * open_unit(a3), s3, c3);
     G[0] = R1 * c1;
     G[1] = R1 * s1;
-    G[2] = R2 * cospi(2.0 * open_unit(a3));
+    G[2] = R2 * c3;
     U = open_unit(b0);
 }
 
@@ -148,7 +129,7 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, doubl
 
     // proposal, eq. (proposal): v' = A(v) v + B(v) G, B = (2/m) zeta^theta P^theta
     const Coef f = fd_coef(P, kpar, kperp, ei, ej, dt);
-    const double b_par = sqrt(f.b2_par), b_perp = sqrt(f.b2_perp);
+    const double b_par = fd_sqrt(f.b2_par), b_perp = fd_sqrt(f.b2_perp);
     const double vpar = vx * ex + vy * ey + vz * ez;
     const double Gpar = G[0] * ex + G[1] * ey + G[2] * ez;
     const double vqx = vx - vpar * ex, vqy = vy - vpar * ey, vqz = vz - vpar * ez;
@@ -186,15 +167,15 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, doubl
                                 + (wqx * wqx + wqy * wqy + wqz * wqz) * fast_rcp(g.b2_perp);
             const double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
             // log|B(v)| - log|B(v')| = (1/2) log(b_par^2 b_perp^4 / (b'_par^2 b'_perp^4))
-            const double logdet = 0.5 * log((f.b2_par * f.b2_perp * f.b2_perp)
+            const double logdet = 0.5 * fd_log((f.b2_par * f.b2_perp * f.b2_perp)
                                             * fast_rcp(g.b2_par * g.b2_perp * g.b2_perp));
             // ideal gas: sum_k (S(eps'_k) - S(eps_k))/kB - log T(eps'_k) + log T(eps_k)
             //          = (Cv/kB - 1) log((1 - delta/ei)(1 - delta/ej))
             const double inv_eiej = fast_rcp(ei * ej);
             const double ui = -delta * ej * inv_eiej, uj = -delta * ei * inv_eiej;
-            const double ent = P.ent_c * log1p(ui + uj + ui * uj);
+            const double ent = P.ent_c * fd_log1p(ui + uj + ui * uj);
             const double a = 0.5 * G2 - 0.5 * quad + logdet + ent;
-            const double lnU = log(U);
+            const double lnU = fd_log(U);
             if (fabs(a - lnU) <= 1e-9) cnt.marginal += 1;
             if (!(lnU <= a)) {                       // reject iff U > exp(a)
                 accept = false;
