@@ -138,7 +138,9 @@ int sdpd_density(sdpd_ctx *ctx, const sdpd_state *state, int update_eps_const_S)
 
 /* Conservative forces, eq. (cons-forces):
  *   f_i = sum_{j != i, r_ij < h} m^2 (P_i/rho_i^2 + P_j/rho_j^2) F_ij r_ij
- * with P from the closure at (eps, rho).  Requires the cell order.        */
+ * with P from the closure at (eps, rho).  Requires sdpd_density since the
+ * last sdpd_build_cells, on the same positions (the partners are the active
+ * pairs it recorded); SDPD_EINVAL otherwise.                              */
 int sdpd_forces(sdpd_ctx *ctx, const sdpd_state *state);
 
 /* One fluctuation/dissipation sweep with time step fd_every * dt: every
@@ -182,11 +184,27 @@ int sdpd_sync(sdpd_ctx *ctx);
 int sdpd_set_timing(sdpd_ctx *ctx, int enable);
 int sdpd_timing(sdpd_ctx *ctx, double ms[5], int64_t launches[5]);
 
-/* Execution-only tuning of the F/D sweep (results do not change): tasks
- * given to one workgroup in phase 0 (cells) and in the face, edge and corner
- * phases (cell pairs whose offset has 1, 2, 3 non-zero components).  Each
- * in 1..64.                                                              */
-int sdpd_tune(sdpd_ctx *ctx, const int32_t fd_tasks[4]);
+/* Execution-only tuning of the F/D sweep (results do not change).  Index k
+ * is the phase class: 0 = phase 0 (pairs inside a cell), 1, 2, 3 = phases of
+ * cell pairs whose offset has 1 (face), 2 (edge), 3 (corner) non-zero
+ * components.
+ *   fd_tasks[k]          tasks (cells or cell pairs) per workgroup, 1..64;
+ *   fd_lds_particles[k]  particles one workgroup stages in LDS, >= 128;
+ *   fd_lds_pairs[k]      pair entries one workgroup sorts in LDS, >= 64.
+ * A workgroup whose tasks need more than its capacity processes them in
+ * several batches.  The LDS of one workgroup, 72 B per particle + 4 B per
+ * pair entry + 1316 B, must fit the device's per-workgroup limit.  Fields
+ * equal to 0 in sdpd_tune keep the current value; sdpd_get_tuning reports
+ * the values in use (the defaults scale with the mean particles per cell).
+ * SDPD_EINVAL for out-of-range values; nothing is changed then.          */
+typedef struct {
+    int32_t fd_tasks[4];
+    int32_t fd_lds_particles[4];
+    int32_t fd_lds_pairs[4];
+} sdpd_tuning;
+
+int sdpd_tune(sdpd_ctx *ctx, const sdpd_tuning *tuning);
+int sdpd_get_tuning(sdpd_ctx *ctx, sdpd_tuning *out);
 
 const char *sdpd_strerror(int status);
 int sdpd_abi_version(void);

@@ -71,7 +71,7 @@ static int check_params(const sdpd_params *P, int nc[3])
         if (nc[k] < 0) return SDPD_EINVAL;
         ncell *= nc[k];
     }
-    if (ncell >= 0xffffffffLL) return SDPD_EINVAL;
+    if (ncell > 0x7fffffffLL) return SDPD_EINVAL;   // one workgroup per cell in a 1-D grid
     return SDPD_OK;
 }
 
@@ -242,10 +242,14 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     const size_t n = (size_t)c->n, nce = (size_t)c->ncell;
     c->nscan_blocks = (int64_t)(((size_t)NMASK * nce + 1023) / 1024) + 1;
     c->obs_blocks = c->n > 0 ? std::min<int64_t>(1024, (c->n + 255) / 256) : 1;
-    c->fd_tasks[0] = 7;
-    c->fd_tasks[1] = 8;
-    c->fd_tasks[2] = 16;
-    c->fd_tasks[3] = 40;
+    {
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) !=
+            hipSuccess || lds <= 0)
+            lds = 65536;
+        c->max_lds = lds;
+    }
+    fd_default_tuning(c);
     // schedule capacity: 64 pairs per particle (a jittered lattice has ~39),
     // and at most 27 list entries per particle (1 own-cell + 2 x 13 tasks)
     c->pair_cap = std::max<int64_t>(64 * c->n, 1024);
@@ -266,7 +270,7 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     rc = rc ? rc : dalloc(&c->trho, n);
     rc = rc ? rc : dalloc(&c->tid, n);
     rc = rc ? rc : dalloc(&c->pi, n);
-    rc = rc ? rc : dalloc(&c->masks, (size_t)NMASK * n);
+    rc = rc ? rc : dalloc(&c->masks, (size_t)NNB * n);
     rc = rc ? rc : dalloc(&c->counters, (size_t)CNT_N);
     rc = rc ? rc : dalloc(&c->err, 1);
     rc = rc ? rc : dalloc(&c->obs_partial, (size_t)c->obs_blocks * 6);
@@ -331,7 +335,7 @@ int sdpd_density(sdpd_ctx *c, const sdpd_state *s, int update_eps_const_S)
 
 int sdpd_forces(sdpd_ctx *c, const sdpd_state *s)
 {
-    if (!c || !state_ok(c, s) || !c->cells_valid) return SDPD_EINVAL;
+    if (!c || !state_ok(c, s) || !c->cells_valid || !c->masks_valid) return SDPD_EINVAL;
     return run_forces(c, s, 0);
 }
 
@@ -437,12 +441,25 @@ int sdpd_timing(sdpd_ctx *c, double ms[5], int64_t launches[5])
     return SDPD_OK;
 }
 
-int sdpd_tune(sdpd_ctx *c, const int32_t fd_tasks[4])
+int sdpd_tune(sdpd_ctx *c, const sdpd_tuning *t)
 {
-    if (!c || !fd_tasks) return SDPD_EINVAL;
-    for (int k = 0; k < 4; ++k)
-        if (fd_tasks[k] < 1 || fd_tasks[k] > 64) return SDPD_EINVAL;
-    for (int k = 0; k < 4; ++k) c->fd_tasks[k] = fd_tasks[k];
+    if (!c || !t) return SDPD_EINVAL;
+    sdpd_tuning u = c->tuning;
+    for (int k = 0; k < 4; ++k) {
+        if (t->fd_tasks[k]) u.fd_tasks[k] = t->fd_tasks[k];
+        if (t->fd_lds_particles[k]) u.fd_lds_particles[k] = t->fd_lds_particles[k];
+        if (t->fd_lds_pairs[k]) u.fd_lds_pairs[k] = t->fd_lds_pairs[k];
+    }
+    const int rc = fd_check_tuning(c, &u);
+    if (rc) return rc;
+    c->tuning = u;
+    return SDPD_OK;
+}
+
+int sdpd_get_tuning(sdpd_ctx *c, sdpd_tuning *out)
+{
+    if (!c || !out) return SDPD_EINVAL;
+    *out = c->tuning;
     return SDPD_OK;
 }
 

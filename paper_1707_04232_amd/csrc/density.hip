@@ -17,10 +17,13 @@ __device__ __forceinline__ double kernel_w(const DevParams &P, double r)
 
 // One thread per particle in cell order.  Candidates are the particles of
 // the 27 cells around the particle's cell, visited in the fixed order
-// (offset index 0..26 with z slowest, then slot), so the sum is
-// deterministic.  For the own cell and the 13 forward cells the bit of
-// every active partner's slot is stored: masks[k * n + i], k = 0 own cell
-// (partners other than i), k = 1..13 forward offsets 14..26.
+// (offset index k = 0..26 with z slowest, then slot), so the sum is
+// deterministic.  The periodic image is chosen per neighbour cell: a cell
+// reached across the box boundary contributes (x_i - x_j) + shift with
+// shift = +-L, which is exactly the minimum-image difference for every pair
+// closer than h (L >= 4 h), in the same rounding as the plain form.  For all
+// 27 cells the bit of every active partner's slot is stored in
+// masks[k * n + i] (the own cell, k = 13, without i itself).
 __global__ __launch_bounds__(256) void k_density(DevParams P, const double *__restrict__ q,
                                                  const uint32_t *__restrict__ cell_sorted,
                                                  const uint32_t *__restrict__ cell_start,
@@ -38,29 +41,25 @@ __global__ __launch_bounds__(256) void k_density(DevParams P, const double *__re
     const double xi = q[i], yi = q[n + i], zi = q[2 * n + i];
     double acc = 0.0;
     for (int k = 0; k < 27; ++k) {
-        int x2 = cx + (k % 3) - 1, y2 = cy + (k / 3) % 3 - 1, z2 = cz + k / 9 - 1;
-        x2 += x2 < 0 ? P.nc[0] : (x2 >= P.nc[0] ? -P.nc[0] : 0);
-        y2 += y2 < 0 ? P.nc[1] : (y2 >= P.nc[1] ? -P.nc[1] : 0);
-        z2 += z2 < 0 ? P.nc[2] : (z2 >= P.nc[2] ? -P.nc[2] : 0);
-        const uint32_t c2 = (uint32_t)(x2 + P.nc[0] * (y2 + P.nc[1] * z2));
-        const uint32_t s = cell_start[c2], e = cell_start[c2 + 1];
+        const NbCell nb = neighbour_cell(P, cx, cy, cz, k);
+        const uint32_t s = cell_start[nb.c], e = cell_start[nb.c + 1];
         uint64_t mask = 0;
         if (e - s > (uint32_t)P.cap) {   // overflowing cell: reported, not visited
             atomicOr(err, ERR_CELLCAP);
-            if (k >= 13) masks[(int64_t)(k - 13) * n + i] = 0ull;
+            masks[(int64_t)k * n + i] = 0ull;
             continue;
         }
         for (uint32_t j = s; j < e; ++j) {
-            double dx = min_image(xi - q[j], P.box[0], P.half_box[0]);
-            double dy = min_image(yi - q[n + j], P.box[1], P.half_box[1]);
-            double dz = min_image(zi - q[2 * n + j], P.box[2], P.half_box[2]);
-            double r2 = dx * dx + dy * dy + dz * dz;
+            const double dx = (xi - q[j]) + nb.sx;
+            const double dy = (yi - q[n + j]) + nb.sy;
+            const double dz = (zi - q[2 * n + j]) + nb.sz;
+            const double r2 = dx * dx + dy * dy + dz * dz;
             if (r2 < P.h2) {
                 acc += P.m * kernel_w(P, sqrt(r2));
-                if (j != (uint32_t)i && j - s < (uint32_t)MAX_CAP) mask |= 1ull << (j - s);
+                if (j != (uint32_t)i) mask |= 1ull << (j - s);
             }
         }
-        if (k >= 13) masks[(int64_t)(k - 13) * n + i] = mask;
+        masks[(int64_t)k * n + i] = mask;
     }
     const double rho_old = rho[i];
     rho[i] = acc;

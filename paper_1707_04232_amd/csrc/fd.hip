@@ -14,54 +14,53 @@
 // order between pairs sharing a particle gives the same result.
 //
 // GPU schedule.  The scheduling pass (schedule.hip) has stored, for every
-// task, its active pairs with their conflict level.  One launch per phase:
-// a workgroup of one wave takes a batch of consecutive tasks of the phase,
-// stages in LDS only the particles that take part in a pair, sorts the
-// batch's pairs by level and applies the pairs of one level (which share no
-// particle) as parallel steps of 64 lanes.
+// task, its active pairs with their conflict level.  A workgroup of one wave
+// takes a range of consecutive tasks of one phase, stages in LDS only the
+// particles that take part in a pair, sorts the range's pairs by level and
+// applies the pairs of one level (which share no particle) as parallel steps
+// of 64 lanes.
+//
+// Phases that touch disjoint cells commute.  Phase 1 + 8 o + pi touches the
+// cells of parity pi (as A) and pi ^ b_o (as B = A + delta_o, b_o the parity
+// bits that delta_o flips; the number of cells per axis is even, so this
+// holds across the periodic boundary).  Each phase is given the level
+// 1 + the largest level of the earlier phases whose parity sets intersect
+// its own; the phases of one level run in one launch, levels in ascending
+// order.  Every pair of phases whose order is exchanged touches disjoint
+// particles, so the result equals the sweep in key order bit for bit.  For
+// the 13 forward offsets this gives 26 launches of 4 phases each.
+#include <algorithm>
+#include <cmath>
+
 #include "fd_math.hpp"
 
 namespace sdpd {
 
-constexpr int FD_MAXTASKS = 64;    // tasks per batch
+constexpr int FD_MAXTASKS = 64;    // tasks per workgroup range
 constexpr int FD_NLVL = 64;        // levels of a task are 1..64
+constexpr int FD_EPL = 32;         // pair entries per lane held in registers
+constexpr int FD_PPL = 8;          // particle-list entries per lane per staging pass
+constexpr int FD_MAXPH = 4;        // phases per launch
 
-struct FdPhase {
-    int phase;          // 0..104
-    int mslot;          // mask / task slot of the phase (0 = own cell)
-    int d[3];           // offset of B relative to A
-    int par[3];         // coordinate parity of A
-    int hx, hy;         // tasks per axis (x, y) of a parity class
-    int64_t ntasks;
-    int64_t tasks_per_wg;
-    int64_t task_base;  // index of the phase's first task in sweep order
+struct FdLaunch {
+    int nph;
+    int cap_p, cap_e;                // LDS capacity: particles, pair entries
+    int64_t task_base[FD_MAXPH];     // index of the phase's first task in sweep order
+    int64_t ntasks[FD_MAXPH];
+    int64_t tpw[FD_MAXPH];           // tasks per workgroup
+    int64_t wg_end[FD_MAXPH];        // cumulative workgroup counts
 };
 
-template <int MAXP, int MAXPAIRS>
-struct FdShared {
-    double q[3][MAXP];
-    double p[3][MAXP];
-    double eps[MAXP];
-    double rho[MAXP];
-    uint32_t id[MAXP];
-    uint32_t gidx[MAXP];
-    uint32_t sorted[MAXPAIRS];       // batch particle index of the A side | B side << 16
-    uint32_t hist[FD_NLVL + 2];
-    uint32_t off[FD_NLVL + 2];
-    uint32_t cur[FD_NLVL + 2];
-    uint32_t eoff[FD_MAXTASKS + 1];  // pair-entry offsets of the workgroup's tasks
-    uint32_t poff[FD_MAXTASKS + 1];  // particle-list offsets of the workgroup's tasks
-    int maxlv;
-};
+// dynamic LDS layout: q[3][cap_p], p[3][cap_p], eps, rho (doubles), then id,
+// gidx, sorted[cap_e] and the small tables (32-bit)
+__host__ __device__ inline size_t fd_lds_bytes(int cap_p, int cap_e)
+{
+    return (size_t)72 * cap_p + (size_t)4 * cap_e + 4 * (3 * (FD_NLVL + 2) + 2 * (FD_MAXTASKS + 1) + 1);
+}
 
 constexpr uint64_t POS_MASK = (1ull << 25) - 1ull;
 
-// One launch per phase; one wave per workgroup; the workgroup's tasks are
-// [blockIdx * tpw, +tpw) (tpw <= 64), applied in batches that fit in LDS
-// (normally one).  A batch's particles and pair entries are contiguous in
-// the schedule written by the scheduling pass.
-template <int MAXP, int MAXPAIRS>
-__global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ Pp, FdPhase ph,
+__global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ Pp, FdLaunch L,
                                                  const double *__restrict__ q, double *p,
                                                  double *eps, const double *__restrict__ rho,
                                                  const uint32_t *__restrict__ id,
@@ -73,29 +72,49 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                                                  uint32_t step, double dt,
                                                  unsigned long long *counters, uint32_t *err)
 {
-    __shared__ FdShared<MAXP, MAXPAIRS> S;
-    constexpr int EPL = MAXPAIRS / 64;   // pair entries per lane in one load pass
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int CP = L.cap_p, CE = L.cap_e;
+    double *s_q = (double *)lds;
+    double *s_p = s_q + 3 * CP;
+    double *s_eps = s_p + 3 * CP;
+    double *s_rho = s_eps + CP;
+    uint32_t *s_id = (uint32_t *)(s_rho + CP);
+    uint32_t *s_gidx = s_id + CP;
+    uint32_t *s_sorted = s_gidx + CP;                 // A-side | B-side << 16
+    uint32_t *s_hist = s_sorted + CE;
+    uint32_t *s_off = s_hist + (FD_NLVL + 2);
+    uint32_t *s_cur = s_off + (FD_NLVL + 2);
+    uint32_t *s_eoff = s_cur + (FD_NLVL + 2);        // pair-entry offsets of the range's tasks
+    uint32_t *s_poff = s_eoff + (FD_MAXTASKS + 1);   // particle-list offsets
+    int *s_maxlv = (int *)(s_poff + (FD_MAXTASKS + 1));
+
     const DevParams &P = *Pp;
     const int lane = threadIdx.x;
     const int64_t n = P.n;
-    const int64_t t0 = (int64_t)blockIdx.x * ph.tasks_per_wg;
-    const int R = (int)(t0 + ph.tasks_per_wg < ph.ntasks ? ph.tasks_per_wg : ph.ntasks - t0);
-    const int64_t T0 = ph.task_base + t0;
+    // phase of this workgroup and its task range
+    int64_t b = blockIdx.x;
+    int k_ph = 0;
+    while (k_ph + 1 < L.nph && b >= L.wg_end[k_ph]) ++k_ph;
+    if (k_ph > 0) b -= L.wg_end[k_ph - 1];
+    const int64_t tpw = L.tpw[k_ph], ntasks = L.ntasks[k_ph], task_base = L.task_base[k_ph];
+    const int64_t t0 = b * tpw;
+    const int R = (int)(t0 + tpw < ntasks ? tpw : ntasks - t0);
+    const int64_t T0 = task_base + t0;
     FdCount cnt = {0u, 0u, 0u, 0u, 0u};
     bool negeps = false;
 
     // offsets of the range's tasks (R + 1 values) and of the phase
     if (lane < R) {
-        S.eoff[lane] = pair_off[T0 + lane];
-        S.poff[lane] = part_off[T0 + lane];
+        s_eoff[lane] = pair_off[T0 + lane];
+        s_poff[lane] = part_off[T0 + lane];
     }
     if (lane == 0) {   // end of the range (R may be 64)
-        S.eoff[R] = pair_off[T0 + R];
-        S.poff[R] = part_off[T0 + R];
+        s_eoff[R] = pair_off[T0 + R];
+        s_poff[R] = part_off[T0 + R];
     }
-    const uint32_t phase_p0 = part_off[ph.task_base];
+    const uint32_t phase_p0 = part_off[task_base];
     __syncthreads();
-    if (S.eoff[R] > pair_cap || S.poff[R] > part_cap) {   // schedule incomplete
+    if (s_eoff[R] > pair_cap || s_poff[R] > part_cap) {   // schedule incomplete
         if (lane == 0) atomicOr(err, ERR_PAIRCAP);
         return;
     }
@@ -106,43 +125,42 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
         const int k0 = k;
         bool oversized = false;
         while (k < R) {
-            const int c = (int)(S.eoff[k + 1] - S.eoff[k]);
-            const int np_new = (int)(S.poff[k + 1] - S.poff[k0]);
-            const int npr_new = (int)(S.eoff[k + 1] - S.eoff[k0]);
-            if (k > k0 && c > 0 && (np_new > MAXP || npr_new > MAXPAIRS)) break;
-            oversized = c > MAXPAIRS;   // only possible as the first task of a batch
+            const int c = (int)(s_eoff[k + 1] - s_eoff[k]);
+            const int np_new = (int)(s_poff[k + 1] - s_poff[k0]);
+            const int npr_new = (int)(s_eoff[k + 1] - s_eoff[k0]);
+            if (k > k0 && c > 0 && (np_new > CP || npr_new > CE)) break;
+            oversized = c > CE;   // only possible as the first task of a batch
             ++k;
             if (oversized) break;
         }
-        const uint32_t e_begin = S.eoff[k0], p_begin = S.poff[k0];
-        const int npr = (int)(S.eoff[k] - e_begin), np = (int)(S.poff[k] - p_begin);
+        const uint32_t e_begin = s_eoff[k0], p_begin = s_poff[k0];
+        const int npr = (int)(s_eoff[k] - e_begin), np = (int)(s_poff[k] - p_begin);
         if (npr == 0) continue;
         const uint32_t rel0 = p_begin - phase_p0;   // list position of batch particle 0
         // ---- stage the particles that take part in a pair: list entries
-        //      first (one round-trip), then all state loads
-        {
-            constexpr int PPL = (MAXP + 63) / 64;
-            uint32_t gl[PPL];
+        //      first (one round-trip per pass), then all state loads
+        for (int base = 0; base < np; base += FD_PPL * 64) {
+            uint32_t gl[FD_PPL];
 #pragma unroll
-            for (int r = 0; r < PPL; ++r) {
-                const int l = r * 64 + lane;
+            for (int r = 0; r < FD_PPL; ++r) {
+                const int l = base + r * 64 + lane;
                 gl[r] = l < np ? part_list[p_begin + l] : 0u;
             }
 #pragma unroll
-            for (int r = 0; r < PPL; ++r) {
-                const int l = r * 64 + lane;
+            for (int r = 0; r < FD_PPL; ++r) {
+                const int l = base + r * 64 + lane;
                 if (l < np) {
                     const int64_t g = gl[r];
-                    S.gidx[l] = (uint32_t)g;
-                    S.q[0][l] = q[g];
-                    S.q[1][l] = q[n + g];
-                    S.q[2][l] = q[2 * n + g];
-                    S.p[0][l] = p[g];
-                    S.p[1][l] = p[n + g];
-                    S.p[2][l] = p[2 * n + g];
-                    S.eps[l] = eps[g];
-                    S.rho[l] = rho[g];
-                    S.id[l] = id[g];
+                    s_gidx[l] = (uint32_t)g;
+                    s_q[l] = q[g];
+                    s_q[CP + l] = q[n + g];
+                    s_q[2 * CP + l] = q[2 * n + g];
+                    s_p[l] = p[g];
+                    s_p[CP + l] = p[n + g];
+                    s_p[2 * CP + l] = p[2 * n + g];
+                    s_eps[l] = eps[g];
+                    s_rho[l] = rho[g];
+                    s_id[l] = id[g];
                 }
             }
         }
@@ -151,95 +169,96 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
         int lo = 1;
         while (lo <= FD_NLVL) {
             int hi = FD_NLVL;
-            S.hist[lane + 1] = 0u;
-            if (lane == 0) S.maxlv = 0;
+            s_hist[lane + 1] = 0u;
+            if (lane == 0) *s_maxlv = 0;
             __syncthreads();
             if (oversized) {
                 for (int e = lane; e < npr; e += 64) {
                     const int lv = (int)(pairs[e_begin + e] >> 50);
-                    if (lv >= 1 && lv <= FD_NLVL) atomicAdd(&S.hist[lv], 1u);
+                    if (lv >= 1 && lv <= FD_NLVL) atomicAdd(&s_hist[lv], 1u);
                 }
                 __syncthreads();
                 int acc = 0;
                 for (hi = lo; hi <= FD_NLVL; ++hi) {
-                    if (acc + (int)S.hist[hi] > MAXPAIRS) break;
-                    acc += (int)S.hist[hi];
+                    if (acc + (int)s_hist[hi] > CE) break;
+                    acc += (int)s_hist[hi];
                 }
                 --hi;
                 hi = hi < lo ? lo : hi;   // one level (<= 64 pairs) always fits
                 __syncthreads();
-                S.hist[lane + 1] = 0u;
+                s_hist[lane + 1] = 0u;
                 __syncthreads();
             }
             // counting sort of the batch's entries by level: histogram pass,
-            // prefix, scatter pass.  Entries stay in registers (EPL per lane)
-            // between the passes unless the batch needs several load passes.
-            uint64_t ebuf[EPL];
-            const bool one_pass = npr <= MAXPAIRS;
-            for (int base = 0; base < npr; base += MAXPAIRS) {
+            // prefix, scatter pass.  Entries stay in registers (FD_EPL per
+            // lane) between the passes unless the batch needs several passes.
+            constexpr int EP = FD_EPL * 64;
+            uint64_t ebuf[FD_EPL];
+            const bool one_pass = npr <= EP;
+            for (int base = 0; base < npr; base += EP) {
 #pragma unroll
-                for (int r = 0; r < EPL; ++r) {
+                for (int r = 0; r < FD_EPL; ++r) {
                     const int x = base + r * 64 + lane;
                     ebuf[r] = x < npr ? pairs[e_begin + x] : 0ull;
                 }
 #pragma unroll
-                for (int r = 0; r < EPL; ++r) {
+                for (int r = 0; r < FD_EPL; ++r) {
                     const int lv = (int)(ebuf[r] >> 50);
-                    if (lv >= lo && lv <= hi && lv <= FD_NLVL) atomicAdd(&S.hist[lv], 1u);
+                    if (lv >= lo && lv <= hi && lv <= FD_NLVL) atomicAdd(&s_hist[lv], 1u);
                 }
             }
             __syncthreads();
             {   // exclusive prefix over levels: lane x holds level x + 1
-                const uint32_t h = S.hist[lane + 1];
+                const uint32_t h = s_hist[lane + 1];
                 uint32_t incl = h;
 #pragma unroll
                 for (int off = 1; off < 64; off <<= 1) {
                     const uint32_t v = (uint32_t)__shfl_up((int)incl, off);
                     if (lane >= off) incl += v;
                 }
-                S.off[lane + 1] = incl - h;
-                S.cur[lane + 1] = incl - h;
+                s_off[lane + 1] = incl - h;
+                s_cur[lane + 1] = incl - h;
                 const uint64_t nz = __ballot(h != 0u);
-                if (lane == 0) S.maxlv = nz ? 64 - __clzll(nz) : 0;
+                if (lane == 0) *s_maxlv = nz ? 64 - __clzll(nz) : 0;
             }
             __syncthreads();
-            for (int base = 0; base < npr; base += MAXPAIRS) {
+            for (int base = 0; base < npr; base += EP) {
                 if (!one_pass) {
 #pragma unroll
-                    for (int r = 0; r < EPL; ++r) {
+                    for (int r = 0; r < FD_EPL; ++r) {
                         const int x = base + r * 64 + lane;
                         ebuf[r] = x < npr ? pairs[e_begin + x] : 0ull;
                     }
                 }
 #pragma unroll
-                for (int r = 0; r < EPL; ++r) {
+                for (int r = 0; r < FD_EPL; ++r) {
                     const uint64_t e = ebuf[r];
                     const int lv = (int)(e >> 50);
                     const int li = (int)((uint32_t)(e & POS_MASK) - rel0);
                     const int lj = (int)((uint32_t)((e >> 25) & POS_MASK) - rel0);
                     if (lv >= lo && lv <= hi && lv <= FD_NLVL && li >= 0 && li < np && lj >= 0 &&
                         lj < np) {
-                        const uint32_t pos = atomicAdd(&S.cur[lv], 1u);
-                        if (pos < (uint32_t)MAXPAIRS) S.sorted[pos] = (uint32_t)li | ((uint32_t)lj << 16);
+                        const uint32_t pos = atomicAdd(&s_cur[lv], 1u);
+                        if (pos < (uint32_t)CE) s_sorted[pos] = (uint32_t)li | ((uint32_t)lj << 16);
                     }
                 }
             }
             __syncthreads();
-            const int top = S.maxlv;
+            const int top = *s_maxlv;
             for (int l = lo; l <= top; ++l) {
-                const int beg = (int)S.off[l], end = beg + (int)S.hist[l];
+                const int beg = (int)s_off[l], end = beg + (int)s_hist[l];
                 for (int b0 = beg; b0 < end; b0 += 64) {
                     const int e = b0 + lane;
                     if (e < end) {
-                        const uint32_t pr = S.sorted[e];
+                        const uint32_t pr = s_sorted[e];
                         int li = (int)(pr & 0xFFFFu), lj = (int)(pr >> 16);
-                        if (S.id[li] > S.id[lj]) {
+                        if (s_id[li] > s_id[lj]) {
                             const int tt = li;
                             li = lj;
                             lj = tt;
                         }
-                        fd_pair<MAXP>(P, step, dt, li, lj, S.q, S.p, S.eps, S.rho, S.id, cnt,
-                                      negeps);
+                        fd_pair(P, step, dt, li, lj, s_q, s_p, CP, s_eps, s_rho, s_id, cnt,
+                                negeps);
                     }
                 }
                 __syncthreads();
@@ -249,11 +268,11 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
         }
         // ---- write back momenta and energies
         for (int l = lane; l < np; l += 64) {
-            const int64_t g = S.gidx[l];
-            p[g] = S.p[0][l];
-            p[n + g] = S.p[1][l];
-            p[2 * n + g] = S.p[2][l];
-            eps[g] = S.eps[l];
+            const int64_t g = s_gidx[l];
+            p[g] = s_p[l];
+            p[n + g] = s_p[CP + l];
+            p[2 * n + g] = s_p[2 * CP + l];
+            eps[g] = s_eps[l];
         }
         __syncthreads();
     }
@@ -272,61 +291,163 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
     }
 }
 
-// LDS sizes.  Phase 0: ~17 particles and ~150 pairs per cell, so about seven
-// cells fill a batch; inter-cell phases: up to 2 x 64 particles per task and
-// fewer pairs.  Any single task fits the particle arrays (<= 128).
-constexpr int FD_INTRA_P = 192, FD_INTRA_PAIRS = 2048;
-constexpr int FD_INTER_P = 384, FD_INTER_PAIRS = 1536;
+// ---------------------------------------------------------------- host side
+
+namespace {
+
+// class of a phase: 0 = own cell, else the number of non-zero components of
+// its offset; parity set: the cell parities the phase touches
+struct PhaseGeom {
+    int cls;
+    unsigned parity_set;
+};
+
+PhaseGeom phase_geom(int phase)
+{
+    PhaseGeom g;
+    if (phase == 0) {
+        g.cls = 0;
+        g.parity_set = 0xFFu;
+        return g;
+    }
+    const int o = (phase - 1) / 8, pi = (phase - 1) % 8, k = 14 + o;
+    const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+    const int b = (dx & 1) | ((dy & 1) << 1) | ((dz & 1) << 2);
+    g.cls = (dx != 0) + (dy != 0) + (dz != 0);
+    g.parity_set = (1u << pi) | (1u << (pi ^ b));
+    return g;
+}
+
+// per-task staging allowance at 17.5 particles per cell: mean participants
+// and pair entries per task, and their spread (standard deviation per task),
+// measured on jittered lattices
+struct Allow {
+    double mp, sp, me, se;
+};
+constexpr Allow kAllow[4] = {
+    {17.5, 5.5, 143.0, 50.0},   // own cell
+    {26.2, 10.0, 102.0, 59.0},  // face
+    {14.7, 10.0, 25.2, 20.0},   // edge
+    {6.7, 5.0, 5.4, 4.5},       // corner
+};
+constexpr int kDefaultTasks[4] = {8, 10, 24, 64};
+
+int round_up(double x, int q)
+{
+    return (int)((std::ceil(x) + q - 1) / q) * q;
+}
+
+}  // namespace
+
+void fd_default_tuning(sdpd_ctx *c)
+{
+    const double s = c->ncell > 0 ? ((double)c->n / (double)c->ncell) / 17.5 : 1.0;
+    const int lim = std::min(c->max_lds, 65536);
+    for (int k = 0; k < 4; ++k) {
+        const int t = kDefaultTasks[k];
+        const double st = std::sqrt((double)t);
+        int cp = round_up((t * kAllow[k].mp + 4.0 * st * kAllow[k].sp) * s, 16);
+        int ce = round_up((t * kAllow[k].me + 4.0 * st * kAllow[k].se) * s * s, 64);
+        cp = std::min(std::max(cp, 128), 65535);
+        ce = std::max(ce, 64);
+        // shrink to the LDS limit, keeping the particle / pair proportion
+        while (fd_lds_bytes(cp, ce) > (size_t)lim && (cp > 128 || ce > 64)) {
+            cp = std::max(128, cp * 7 / 8);
+            ce = std::max(64, ce * 7 / 8);
+        }
+        c->tuning.fd_tasks[k] = t;
+        c->tuning.fd_lds_particles[k] = cp;
+        c->tuning.fd_lds_pairs[k] = ce;
+    }
+    if (c->max_lds > 65536) {
+        // allow dynamic LDS beyond 64 KiB where the device has it
+        if (hipFuncSetAttribute((const void *)k_fd_phase,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                c->max_lds) != hipSuccess) {
+            (void)hipGetLastError();
+            c->max_lds = 65536;
+        }
+    }
+}
+
+int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t)
+{
+    for (int k = 0; k < 4; ++k) {
+        if (t->fd_tasks[k] < 1 || t->fd_tasks[k] > FD_MAXTASKS) return SDPD_EINVAL;
+        if (t->fd_lds_particles[k] < 128 || t->fd_lds_particles[k] > 65535) return SDPD_EINVAL;
+        if (t->fd_lds_pairs[k] < 64 || t->fd_lds_pairs[k] > (1 << 24)) return SDPD_EINVAL;
+        if (fd_lds_bytes(t->fd_lds_particles[k], t->fd_lds_pairs[k]) > (size_t)c->max_lds)
+            return SDPD_EINVAL;
+    }
+    return SDPD_OK;
+}
+
+// one launch over the tasks of up to FD_MAXPH mutually disjoint phases
+static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, int nph,
+                         uint64_t step, double dt_fd)
+{
+    FdLaunch L;
+    L.nph = nph;
+    L.cap_p = 0;
+    L.cap_e = 0;
+    int64_t wg = 0;
+    for (int k = 0; k < FD_MAXPH; ++k) {
+        L.task_base[k] = L.ntasks[k] = L.wg_end[k] = 0;
+        L.tpw[k] = 1;
+    }
+    for (int k = 0; k < nph; ++k) {
+        const int ph = phases[k];
+        const int cls = phase_geom(ph).cls;
+        L.task_base[k] = ph == 0 ? 0 : c->ncell + (int64_t)(ph - 1) * (c->ncell / 8);
+        L.ntasks[k] = ph == 0 ? c->ncell : c->ncell / 8;
+        L.tpw[k] = c->tuning.fd_tasks[cls];
+        wg += (L.ntasks[k] + L.tpw[k] - 1) / L.tpw[k];
+        L.wg_end[k] = wg;
+        L.cap_p = std::max(L.cap_p, (int)c->tuning.fd_lds_particles[cls]);
+        L.cap_e = std::max(L.cap_e, (int)c->tuning.fd_lds_pairs[cls]);
+    }
+    if (wg == 0) return SDPD_OK;
+    if (wg > 0x7fffffffLL) return SDPD_EINVAL;
+    const size_t lds = fd_lds_bytes(L.cap_p, L.cap_e);
+    if (lds > (size_t)c->max_lds) return SDPD_EINVAL;
+    timer_begin(c, TK_FD);
+    hipLaunchKernelGGL(k_fd_phase, dim3((unsigned)wg), dim3(64), lds, c->stream, c->dparams, L,
+                       s->q, s->p, s->eps, s->rho, s->id, c->pair_off, c->part_off, c->pairs,
+                       c->part_list, (uint32_t)c->pair_cap, (uint32_t)c->part_cap,
+                       (uint32_t)step, dt_fd, c->counters, c->err);
+    timer_end(c, TK_FD);
+    return check_hip(hipGetLastError());
+}
 
 int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, uint64_t step, double dt_fd)
 {
     if (c->prm.fd == SDPD_FD_NONE || c->n == 0) return SDPD_OK;
     int rc = run_schedule(c);
     if (rc) return rc;
-    const int *nc = c->dp.nc;
-    for (int phase = 0; phase <= 104; ++phase) {
-        FdPhase ph;
-        ph.phase = phase;
-        if (phase == 0) {
-            ph.mslot = 0;
-            ph.d[0] = ph.d[1] = ph.d[2] = 0;
-            ph.par[0] = ph.par[1] = ph.par[2] = 0;
-            ph.hx = ph.hy = 0;
-            ph.ntasks = c->ncell;
-            ph.tasks_per_wg = c->fd_tasks[0];
-            ph.task_base = 0;
-        } else {
-            const int o = (phase - 1) / 8, pi = (phase - 1) % 8, k = 14 + o;
-            ph.mslot = o + 1;
-            ph.d[0] = k % 3 - 1;
-            ph.d[1] = (k / 3) % 3 - 1;
-            ph.d[2] = k / 9 - 1;
-            ph.par[0] = pi & 1;
-            ph.par[1] = (pi >> 1) & 1;
-            ph.par[2] = (pi >> 2) & 1;
-            ph.hx = nc[0] / 2;
-            ph.hy = nc[1] / 2;
-            ph.ntasks = c->ncell / 8;
-            const int cls = (ph.d[0] != 0) + (ph.d[1] != 0) + (ph.d[2] != 0);   // 1, 2, 3
-            ph.tasks_per_wg = c->fd_tasks[cls];
-            ph.task_base = c->ncell + (int64_t)(phase - 1) * (c->ncell / 8);
+    const int zero = 0;
+    if ((rc = launch_phases(c, s, &zero, 1, step, dt_fd))) return rc;
+    // levels of the inter-cell phases (phase 0 touches every cell and runs first)
+    int lvl[105];
+    unsigned set[105];
+    int maxl = 0;
+    for (int p = 1; p <= 104; ++p) {
+        set[p] = phase_geom(p).parity_set;
+        lvl[p] = 1;
+        for (int r = 1; r < p; ++r)
+            if ((set[r] & set[p]) && lvl[r] + 1 > lvl[p]) lvl[p] = lvl[r] + 1;
+        maxl = std::max(maxl, lvl[p]);
+    }
+    for (int l = 1; l <= maxl; ++l) {
+        int group[FD_MAXPH], ng = 0;
+        for (int p = 1; p <= 104; ++p) {
+            if (lvl[p] != l) continue;
+            group[ng++] = p;
+            if (ng == FD_MAXPH) {
+                if ((rc = launch_phases(c, s, group, ng, step, dt_fd))) return rc;
+                ng = 0;
+            }
         }
-        const int64_t grid = (ph.ntasks + ph.tasks_per_wg - 1) / ph.tasks_per_wg;
-        timer_begin(c, TK_FD);
-        if (phase == 0)
-            hipLaunchKernelGGL((k_fd_phase<FD_INTRA_P, FD_INTRA_PAIRS>), dim3((unsigned)grid),
-                               dim3(64), 0, c->stream, c->dparams, ph, s->q, s->p, s->eps, s->rho,
-                               s->id, c->pair_off, c->part_off, c->pairs, c->part_list,
-                               (uint32_t)c->pair_cap, (uint32_t)c->part_cap, (uint32_t)step,
-                               dt_fd, c->counters, c->err);
-        else
-            hipLaunchKernelGGL((k_fd_phase<FD_INTER_P, FD_INTER_PAIRS>), dim3((unsigned)grid),
-                               dim3(64), 0, c->stream, c->dparams, ph, s->q, s->p, s->eps, s->rho,
-                               s->id, c->pair_off, c->part_off, c->pairs, c->part_list,
-                               (uint32_t)c->pair_cap, (uint32_t)c->part_cap, (uint32_t)step,
-                               dt_fd, c->counters, c->err);
-        timer_end(c, TK_FD);
-        if ((rc = check_hip(hipGetLastError()))) return rc;
+        if (ng && (rc = launch_phases(c, s, group, ng, step, dt_fd))) return rc;
     }
     return SDPD_OK;
 }

@@ -95,18 +95,17 @@ struct FdCount {
 };
 
 // One pair update on LDS-resident state; li has the smaller id.  s_q and s_p
-// hold the x, y, z planes at stride MAXP.
-template <int MAXP>
+// hold the x, y, z planes at stride ps.
 __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, double dt, int li,
-                                        int lj, double (*s_q)[MAXP], double (*s_p)[MAXP],
+                                        int lj, const double *s_q, double *s_p, int ps,
                                         double *s_eps, const double *s_rho,
                                         const uint32_t *s_id, FdCount &cnt, bool &negeps)
 {
 #pragma clang fp contract(fast)
     // geometry (Sec. 2.1.1): r_ij, e_ij, F_ij
-    const double dx = min_image(s_q[0][li] - s_q[0][lj], P.box[0], P.half_box[0]);
-    const double dy = min_image(s_q[1][li] - s_q[1][lj], P.box[1], P.half_box[1]);
-    const double dz = min_image(s_q[2][li] - s_q[2][lj], P.box[2], P.half_box[2]);
+    const double dx = min_image(s_q[li] - s_q[lj], P.box[0], P.half_box[0]);
+    const double dy = min_image(s_q[ps + li] - s_q[ps + lj], P.box[1], P.half_box[1]);
+    const double dz = min_image(s_q[2 * ps + li] - s_q[2 * ps + lj], P.box[2], P.half_box[2]);
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double inv_r = fast_rsq(r2);
     const double r = r2 * inv_r;
@@ -120,9 +119,9 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, doubl
     const double kpar = P.kpar_c * kfac, kperp = P.kperp_c * kfac;
 
     const double ei = s_eps[li], ej = s_eps[lj];
-    const double vx = (s_p[0][li] - s_p[0][lj]) * P.inv_m;
-    const double vy = (s_p[1][li] - s_p[1][lj]) * P.inv_m;
-    const double vz = (s_p[2][li] - s_p[2][lj]) * P.inv_m;
+    const double vx = (s_p[li] - s_p[lj]) * P.inv_m;
+    const double vy = (s_p[ps + li] - s_p[ps + lj]) * P.inv_m;
+    const double vz = (s_p[2 * ps + li] - s_p[2 * ps + lj]) * P.inv_m;
 
     double G[3], U;
     pair_draws(P, step, s_id[li], s_id[lj], G, U);
@@ -186,12 +185,12 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, doubl
     if (accept) {
         const double hm = P.m_over_2;
         const double dpx = hm * (nvx - vx), dpy = hm * (nvy - vy), dpz = hm * (nvz - vz);
-        s_p[0][li] += dpx;
-        s_p[1][li] += dpy;
-        s_p[2][li] += dpz;
-        s_p[0][lj] -= dpx;
-        s_p[1][lj] -= dpy;
-        s_p[2][lj] -= dpz;
+        s_p[li] += dpx;
+        s_p[ps + li] += dpy;
+        s_p[2 * ps + li] += dpz;
+        s_p[lj] -= dpx;
+        s_p[ps + lj] -= dpy;
+        s_p[2 * ps + lj] -= dpz;
         s_eps[li] = ei - delta;
         s_eps[lj] = ej - delta;
     }

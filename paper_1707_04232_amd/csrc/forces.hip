@@ -22,14 +22,17 @@ __global__ void k_pressure_term(DevParams P, const double *eps, const double *rh
     if (i < P.n) pi[i] = P.cPi * eps[i] / rho[i];
 }
 
-// f_i = sum_{j != i, r < h} m^2 (Pi_i + Pi_j) F_ij r_ij, candidates in the
-// fixed 27-cell order; optionally p_i += dt/2 f_i.
+// f_i = sum_{j != i, r < h} m^2 (Pi_i + Pi_j) F_ij r_ij over the partners
+// recorded in the 27 active-pair masks of the density pass (same positions),
+// in the fixed order (offset index, then slot); optionally p_i += dt/2 f_i.
+// The masks are read first (27 independent loads), then the set bits are
+// visited as one flat sequence.
 __global__ __launch_bounds__(256) void k_forces(DevParams P, const double *__restrict__ q,
                                                 const double *__restrict__ pi,
                                                 const uint32_t *__restrict__ cell_sorted,
                                                 const uint32_t *__restrict__ cell_start,
-                                                double *f, double *p, int half_kick,
-                                                uint32_t *err)
+                                                const uint64_t *__restrict__ masks,
+                                                double *f, double *p, int half_kick)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
@@ -43,27 +46,21 @@ __global__ __launch_bounds__(256) void k_forces(DevParams P, const double *__res
     const double m2 = P.m * P.m;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     for (int k = 0; k < 27; ++k) {
-        int x2 = cx + (k % 3) - 1, y2 = cy + (k / 3) % 3 - 1, z2 = cz + k / 9 - 1;
-        x2 += x2 < 0 ? P.nc[0] : (x2 >= P.nc[0] ? -P.nc[0] : 0);
-        y2 += y2 < 0 ? P.nc[1] : (y2 >= P.nc[1] ? -P.nc[1] : 0);
-        z2 += z2 < 0 ? P.nc[2] : (z2 >= P.nc[2] ? -P.nc[2] : 0);
-        const uint32_t c2 = (uint32_t)(x2 + P.nc[0] * (y2 + P.nc[1] * z2));
-        const uint32_t s = cell_start[c2], e = cell_start[c2 + 1];
-        if (e - s > (uint32_t)P.cap) {   // overflowing cell: reported, not visited
-            atomicOr(err, ERR_CELLCAP);
-            continue;
-        }
-        for (uint32_t j = s; j < e; ++j) {
-            double dx = min_image(xi - q[j], P.box[0], P.half_box[0]);
-            double dy = min_image(yi - q[n + j], P.box[1], P.half_box[1]);
-            double dz = min_image(zi - q[2 * n + j], P.box[2], P.half_box[2]);
-            double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < P.h2 && j != (uint32_t)i) {
-                double sc = m2 * (pii + pi[j]) * kernel_f(P, sqrt(r2));
-                fx += sc * dx;
-                fy += sc * dy;
-                fz += sc * dz;
-            }
+        uint64_t mask = masks[(int64_t)k * n + i];
+        if (!mask) continue;
+        const NbCell nb = neighbour_cell(P, cx, cy, cz, k);
+        const uint32_t s = cell_start[nb.c];
+        while (mask) {
+            const uint32_t j = s + (uint32_t)__builtin_ctzll(mask);
+            mask &= mask - 1ull;
+            const double dx = (xi - q[j]) + nb.sx;
+            const double dy = (yi - q[n + j]) + nb.sy;
+            const double dz = (zi - q[2 * n + j]) + nb.sz;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double sc = m2 * (pii + pi[j]) * kernel_f(P, sqrt(r2));
+            fx += sc * dx;
+            fy += sc * dy;
+            fz += sc * dz;
         }
     }
     f[i] = fx;
@@ -85,7 +82,7 @@ int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick)
     hipLaunchKernelGGL(k_pressure_term, dim3(g), dim3(256), 0, c->stream, c->dp, s->eps, s->rho,
                        c->pi);
     hipLaunchKernelGGL(k_forces, dim3(g), dim3(256), 0, c->stream, c->dp, s->q, c->pi,
-                       c->cell_sorted, c->cell_start, s->f, s->p, half_kick, c->err);
+                       c->cell_sorted, c->cell_start, c->masks, s->f, s->p, half_kick);
     int rc = check_hip(hipGetLastError());
     timer_end(c, TK_FORCE);
     return rc;

@@ -72,7 +72,7 @@ __global__ void k_task_count(const DevParams *__restrict__ Pp,
     uint64_t orb = 0;
     if (nA <= (uint32_t)P.cap && nB <= (uint32_t)P.cap) {
         for (uint32_t a = 0; a < nA; ++a) {
-            const uint64_t m = masks[(int64_t)tc.slot * P.n + sA + a];
+            const uint64_t m = masks[(int64_t)(OWN_NB + tc.slot) * P.n + sA + a];
             na += m != 0ull;
             orb |= m;
             c += (uint32_t)__popcll(tc.slot == 0 ? (m & ~((2ull << a) - 1ull)) : m);
@@ -107,7 +107,8 @@ __global__ __launch_bounds__(64) void k_schedule(const DevParams *__restrict__ P
             if (lane == 0) atomicOr(err, ERR_PAIRCAP);
             continue;
         }
-        const uint64_t mask = (uint32_t)lane < nA ? masks[(int64_t)tc.slot * P.n + sA + lane] : 0ull;
+        const uint64_t mask =
+            (uint32_t)lane < nA ? masks[(int64_t)(OWN_NB + tc.slot) * P.n + sA + lane] : 0ull;
         const uint64_t actA = __ballot(mask != 0ull);
         const uint64_t actB = intra ? actA : wave_or64(mask);
         const uint32_t nactA = (uint32_t)__popcll(actA);

@@ -16,9 +16,13 @@ enum : uint32_t { ERR_CELLCAP = 1u, ERR_NEGEPS = 2u, ERR_NONFINITE = 4u, ERR_PAI
 // F/D counters, in this order in the device counter array
 enum { CNT_PROPOSED = 0, CNT_REJ_ENERGY, CNT_REJ_RATIO, CNT_MARGINAL, CNT_NEGEPS, CNT_N };
 
-// number of 64-bit active-pair masks per particle: slot 0 = own cell, slots
-// 1..13 = the 13 forward neighbour cells
+// tasks per cell of the F/D schedule: slot 0 = own cell, slots 1..13 = the
+// 13 forward neighbour cells
 constexpr int NMASK = 14;
+// active-pair masks per particle: one per neighbour cell, offset index
+// k = 0..26 (z slowest); k = 13 is the own cell, 14..26 the forward cells
+constexpr int NNB = 27;
+constexpr int OWN_NB = 13;
 constexpr int MAX_CAP = 64;
 
 // Everything a kernel needs, by value.  Derived constants are computed once
@@ -74,7 +78,7 @@ struct sdpd_ctx {
     double *tq, *tp, *teps, *trho, *tf;
     uint32_t *tid;
     double *pi;                  // P/rho^2 per particle
-    uint64_t *masks;             // NMASK * n
+    uint64_t *masks;             // NNB * n
     unsigned long long *counters;
     uint32_t *err;
     double *obs_partial;         // per-block observable partials
@@ -82,7 +86,8 @@ struct sdpd_ctx {
     double *obs_out;             // device stats records
     int64_t obs_cap;
     int cells_valid, masks_valid;
-    int fd_tasks[4];             // tasks per F/D workgroup: own cell, face, edge, corner phases
+    sdpd_tuning tuning;          // F/D workgroup sizes and LDS capacities per phase class
+    int max_lds;                 // LDS bytes one workgroup may use
     // pair schedule (rebuilt before every sweep)
     uint32_t *task_count, *task_np, *pair_off, *part_off, *part_list;
     uint64_t *pairs;
@@ -107,6 +112,8 @@ int run_build_cells(sdpd_ctx *c, const sdpd_state *s, int kick_drift);
 int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps);
 int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick);
 int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, uint64_t step, double dt_fd);
+void fd_default_tuning(sdpd_ctx *c);
+int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t);
 int run_observe(sdpd_ctx *c, const sdpd_state *s, double *dst_record);
 
 // event timing around one launch of class k (no-op unless c->timing)
@@ -125,6 +132,27 @@ __device__ __forceinline__ double min_image(double d, double box, double half)
     if (d > half) return d - box;
     if (d < -half) return d + box;
     return d;
+}
+
+// neighbour cell k (offset index 0..26, z slowest) of cell (cx, cy, cz) and
+// the periodic shift that turns x_i - x_j into the minimum image for it
+struct NbCell {
+    int64_t c;
+    double sx, sy, sz;
+};
+
+__device__ __forceinline__ NbCell neighbour_cell(const DevParams &P, int cx, int cy, int cz, int k)
+{
+    NbCell r;
+    int x2 = cx + (k % 3) - 1, y2 = cy + (k / 3) % 3 - 1, z2 = cz + k / 9 - 1;
+    r.sx = x2 < 0 ? P.box[0] : (x2 >= P.nc[0] ? -P.box[0] : 0.0);
+    r.sy = y2 < 0 ? P.box[1] : (y2 >= P.nc[1] ? -P.box[1] : 0.0);
+    r.sz = z2 < 0 ? P.box[2] : (z2 >= P.nc[2] ? -P.box[2] : 0.0);
+    x2 += x2 < 0 ? P.nc[0] : (x2 >= P.nc[0] ? -P.nc[0] : 0);
+    y2 += y2 < 0 ? P.nc[1] : (y2 >= P.nc[1] ? -P.nc[1] : 0);
+    z2 += z2 < 0 ? P.nc[2] : (z2 >= P.nc[2] ? -P.nc[2] : 0);
+    r.c = x2 + (int64_t)P.nc[0] * (y2 + (int64_t)P.nc[1] * z2);
+    return r;
 }
 
 __device__ __forceinline__ int cell_coord(double x, double inv_cell, int nc)

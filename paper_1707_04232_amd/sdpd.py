@@ -21,7 +21,8 @@ TIMING_CLASSES = ("cells", "density", "fd", "forces", "observe")
 EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
            "sdpd_copy_cell_start", "sdpd_density",
            "sdpd_forces", "sdpd_fd_metropolis", "sdpd_step", "sdpd_observe", "sdpd_sync",
-           "sdpd_set_timing", "sdpd_timing", "sdpd_tune", "sdpd_strerror", "sdpd_abi_version")
+           "sdpd_set_timing", "sdpd_timing", "sdpd_tune", "sdpd_get_tuning", "sdpd_strerror",
+           "sdpd_abi_version")
 
 
 class _Params(C.Structure):
@@ -37,6 +38,11 @@ class _Params(C.Structure):
 class _State(C.Structure):
     _fields_ = [("q", C.c_void_p), ("p", C.c_void_p), ("eps", C.c_void_p),
                 ("rho", C.c_void_p), ("f", C.c_void_p), ("id", C.c_void_p)]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("fd_tasks", C.c_int32 * 4), ("fd_lds_particles", C.c_int32 * 4),
+                ("fd_lds_pairs", C.c_int32 * 4)]
 
 
 class _Stats(C.Structure):
@@ -79,7 +85,8 @@ def lib():
             "sdpd_sync": [vp],
             "sdpd_set_timing": [vp, i32],
             "sdpd_timing": [vp, C.POINTER(C.c_double), C.POINTER(i64)],
-            "sdpd_tune": [vp, C.POINTER(C.c_int32)],
+            "sdpd_tune": [vp, C.POINTER(_Tuning)],
+            "sdpd_get_tuning": [vp, C.POINTER(_Tuning)],
             "sdpd_abi_version": [],
         }
         for name, args in sig.items():
@@ -250,10 +257,23 @@ class Context:
         _check(lib().sdpd_timing(self._h, ms, cnt), "sdpd_timing")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(TIMING_CLASSES)}
 
-    def tune(self, fd_tasks):
-        """tasks per F/D workgroup: (own cell, face, edge, corner) phases."""
-        arr = (C.c_int32 * 4)(*[int(x) for x in fd_tasks])
-        _check(lib().sdpd_tune(self._h, arr), "sdpd_tune")
+    def tune(self, fd_tasks=None, lds_particles=None, lds_pairs=None):
+        """F/D execution tuning per phase class (own cell, face, edge, corner):
+        tasks per workgroup and the LDS capacity of a workgroup; None or 0
+        keeps the current value."""
+        t = _Tuning()
+        for field, vals in (("fd_tasks", fd_tasks), ("fd_lds_particles", lds_particles),
+                            ("fd_lds_pairs", lds_pairs)):
+            arr = getattr(t, field)
+            for k, v in enumerate(vals or (0, 0, 0, 0)):
+                arr[k] = int(v)
+        _check(lib().sdpd_tune(self._h, C.byref(t)), "sdpd_tune")
+
+    def get_tuning(self) -> dict:
+        t = _Tuning()
+        _check(lib().sdpd_get_tuning(self._h, C.byref(t)), "sdpd_get_tuning")
+        return {"fd_tasks": tuple(t.fd_tasks), "lds_particles": tuple(t.fd_lds_particles),
+                "lds_pairs": tuple(t.fd_lds_pairs)}
 
     def prepare(self, s: DeviceState):
         """cells, density without energy update, forces: the entry state of step()."""

@@ -44,11 +44,12 @@ def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     fields = [("sdpd_params", f) for f, _ in sdpd._Params._fields_] + \
              [("sdpd_state", f) for f, _ in sdpd._State._fields_] + \
-             [("sdpd_stats", f) for f, _ in sdpd._Stats._fields_]
+             [("sdpd_stats", f) for f, _ in sdpd._Stats._fields_] + \
+             [("sdpd_tuning", f) for f, _ in sdpd._Tuning._fields_]
     body = "\n".join(f'printf("%zu\\n", offsetof({t}, {f}));' for t, f in fields)
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"sdpd.h\"\nint main(void){\n"
-                   + body + '\nprintf("%zu %zu %zu\\n", sizeof(sdpd_params), sizeof(sdpd_state),'
-                   ' sizeof(sdpd_stats));\nreturn 0;}\n')
+                   + body + '\nprintf("%zu %zu %zu %zu\\n", sizeof(sdpd_params), sizeof(sdpd_state),'
+                   ' sizeof(sdpd_stats), sizeof(sdpd_tuning));\nreturn 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
                    check=True)
@@ -57,7 +58,9 @@ def test_struct_layout_matches_header(tmp_path):
     want = [getattr(sdpd._Params, f).offset for f, _ in sdpd._Params._fields_] + \
            [getattr(sdpd._State, f).offset for f, _ in sdpd._State._fields_] + \
            [getattr(sdpd._Stats, f).offset for f, _ in sdpd._Stats._fields_] + \
-           [C.sizeof(sdpd._Params), C.sizeof(sdpd._State), C.sizeof(sdpd._Stats)]
+           [getattr(sdpd._Tuning, f).offset for f, _ in sdpd._Tuning._fields_] + \
+           [C.sizeof(sdpd._Params), C.sizeof(sdpd._State), C.sizeof(sdpd._Stats),
+            C.sizeof(sdpd._Tuning)]
     assert got == want
 
 

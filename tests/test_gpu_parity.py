@@ -148,16 +148,39 @@ def test_fd_sweep_parity(name, dims, Cv, T, dt, mode, kernel, zeta):
 
 def test_fd_sweep_tuning_does_not_change_results():
     say("fd sweep tuning invariance")
+    sdpd = sd()
     outs = []
-    for tasks in ((9, 12, 16, 26), (1, 1, 1, 1), (3, 5, 2, 7), (64, 64, 64, 64)):
+    configs = [
+        None,                                                    # defaults
+        dict(fd_tasks=(1, 1, 1, 1)),
+        # tiny LDS: most batches split, many tasks take the level-window path
+        dict(fd_tasks=(3, 5, 2, 7), lds_particles=(128,) * 4, lds_pairs=(64,) * 4),
+        dict(fd_tasks=(64, 64, 64, 64), lds_particles=(640,) * 4, lds_pairs=(2048,) * 4),
+        dict(fd_tasks=(9, 12, 16, 26), lds_particles=(256, 200, 300, 400),
+             lds_pairs=(512, 1024, 256, 128)),
+    ]
+    for cfg in configs:
         gp, op, S, R = _fd_case((24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0)
         with sd().Context(gp) as ctx:
-            ctx.tune(tasks)
+            if cfg:
+                ctx.tune(**cfg)
+                t = ctx.get_tuning()
+                assert t["fd_tasks"] == cfg["fd_tasks"]
             ctx.prepare(S)
             ctx.fd_metropolis(S, step=3)
         outs.append(S.to_numpy())
     for o in outs[1:]:
         assert np.array_equal(o["p"], outs[0]["p"]) and np.array_equal(o["eps"], outs[0]["eps"])
+    say("tuning: invalid values are rejected and change nothing")
+    gp, op, S, R = _fd_case((24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0)
+    with sd().Context(gp) as ctx:
+        before = ctx.get_tuning()
+        for bad in (dict(fd_tasks=(65, 1, 1, 1)), dict(lds_particles=(100, 0, 0, 0)),
+                    dict(lds_pairs=(0, 32, 0, 0)), dict(lds_particles=(65535,) * 4)):
+            with pytest.raises(sdpd.SdpdError) as e:
+                ctx.tune(**bad)
+            assert e.value.rc == sdpd.EINVAL
+        assert ctx.get_tuning() == before
 
 
 def _run_steps(dims, nsteps, **kw):
@@ -228,6 +251,8 @@ def test_errors_are_reported():
         ctx.build_cells(S)
         with pytest.raises(sdpd.SdpdError):
             ctx.fd_metropolis(S, 0)
+        with pytest.raises(sdpd.SdpdError):   # forces use the density pass's pair masks
+            ctx.forces(S)
     torch.cuda.synchronize()
 
 
