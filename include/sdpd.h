@@ -192,7 +192,7 @@ int sdpd_timing(sdpd_ctx *ctx, double ms[5], int64_t launches[5]);
  *   fd_lds_particles[k]  particles one workgroup stages in LDS, >= 128;
  *   fd_lds_pairs[k]      pair entries one workgroup sorts in LDS, >= 64.
  * A workgroup whose tasks need more than its capacity processes them in
- * several batches.  The LDS of one workgroup, 72 B per particle + 4 B per
+ * several batches.  The LDS of one workgroup, 36 B per particle + 4 B per
  * pair entry + 1316 B, must fit the device's per-workgroup limit.  Fields
  * equal to 0 in sdpd_tune keep the current value; sdpd_get_tuning reports
  * the values in use (the defaults scale with the mean particles per cell).

@@ -15,10 +15,13 @@
 //
 // GPU schedule.  The scheduling pass (schedule.hip) has stored, for every
 // task, its active pairs with their conflict level.  A workgroup of one wave
-// takes a range of consecutive tasks of one phase, stages in LDS only the
-// particles that take part in a pair, sorts the range's pairs by level and
-// applies the pairs of one level (which share no particle) as parallel steps
-// of 64 lanes.
+// takes a range of consecutive tasks of one phase, stages in LDS the
+// momenta and energies of the particles that take part in a pair, sorts the
+// range's pairs by level and applies the pairs of one level (which share no
+// particle) as parallel steps of 64 lanes.  Positions, densities and ids do
+// not change during the sweep: they are read from global memory, one level
+// step ahead of their use, which keeps the LDS footprint at 36 B per
+// particle and leaves room for more resident waves.
 //
 // Phases that touch disjoint cells commute.  Phase 1 + 8 o + pi touches the
 // cells of parity pi (as A) and pi ^ b_o (as B = A + delta_o, b_o the parity
@@ -38,7 +41,7 @@ namespace sdpd {
 
 constexpr int FD_MAXTASKS = 64;    // tasks per workgroup range
 constexpr int FD_NLVL = 64;        // levels of a task are 1..64
-constexpr int FD_EPL = 32;         // pair entries per lane held in registers
+constexpr int FD_EPL = 16;         // pair entries per lane held in registers
 constexpr int FD_PPL = 8;          // particle-list entries per lane per staging pass
 constexpr int FD_MAXPH = 4;        // phases per launch
 
@@ -51,11 +54,35 @@ struct FdLaunch {
     int64_t wg_end[FD_MAXPH];        // cumulative workgroup counts
 };
 
-// dynamic LDS layout: q[3][cap_p], p[3][cap_p], eps, rho (doubles), then id,
-// gidx, sorted[cap_e] and the small tables (32-bit)
+// dynamic LDS layout: p[3][cap_p], eps[cap_p] (doubles), then gidx[cap_p],
+// sorted[cap_e] and the small tables (32-bit)
 __host__ __device__ inline size_t fd_lds_bytes(int cap_p, int cap_e)
 {
-    return (size_t)72 * cap_p + (size_t)4 * cap_e + 4 * (3 * (FD_NLVL + 2) + 2 * (FD_MAXTASKS + 1) + 1);
+    return (size_t)36 * cap_p + (size_t)4 * cap_e + 4 * (3 * (FD_NLVL + 2) + 2 * (FD_MAXTASKS + 1) + 1);
+}
+
+// read-only data of the pair at sorted position e (batch particle indices
+// li, lj from the LDS list); loads are issued, not waited for
+__device__ __forceinline__ void fd_gather(const uint32_t *s_sorted, const uint32_t *s_gidx,
+                                          const double *__restrict__ q,
+                                          const double *__restrict__ rho,
+                                          const uint32_t *__restrict__ id, int64_t n, int e,
+                                          int &li, int &lj, PairGeo &g)
+{
+    const uint32_t pr = s_sorted[e];
+    li = (int)(pr & 0xFFFFu);
+    lj = (int)(pr >> 16);
+    const int64_t gi = s_gidx[li], gj = s_gidx[lj];
+    g.xi = q[gi];
+    g.yi = q[n + gi];
+    g.zi = q[2 * n + gi];
+    g.xj = q[gj];
+    g.yj = q[n + gj];
+    g.zj = q[2 * n + gj];
+    g.rho_i = rho[gi];
+    g.rho_j = rho[gj];
+    g.id_i = id[gi];
+    g.id_j = id[gj];
 }
 
 constexpr uint64_t POS_MASK = (1ull << 25) - 1ull;
@@ -74,12 +101,9 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const int CP = L.cap_p, CE = L.cap_e;
-    double *s_q = (double *)lds;
-    double *s_p = s_q + 3 * CP;
+    double *s_p = (double *)lds;
     double *s_eps = s_p + 3 * CP;
-    double *s_rho = s_eps + CP;
-    uint32_t *s_id = (uint32_t *)(s_rho + CP);
-    uint32_t *s_gidx = s_id + CP;
+    uint32_t *s_gidx = (uint32_t *)(s_eps + CP);
     uint32_t *s_sorted = s_gidx + CP;                 // A-side | B-side << 16
     uint32_t *s_hist = s_sorted + CE;
     uint32_t *s_off = s_hist + (FD_NLVL + 2);
@@ -137,8 +161,9 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
         const int npr = (int)(s_eoff[k] - e_begin), np = (int)(s_poff[k] - p_begin);
         if (npr == 0) continue;
         const uint32_t rel0 = p_begin - phase_p0;   // list position of batch particle 0
-        // ---- stage the particles that take part in a pair: list entries
-        //      first (one round-trip per pass), then all state loads
+        // ---- stage momenta and energies of the particles that take part in
+        //      a pair: list entries first (one round-trip per pass), then the
+        //      state loads
         for (int base = 0; base < np; base += FD_PPL * 64) {
             uint32_t gl[FD_PPL];
 #pragma unroll
@@ -152,15 +177,10 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                 if (l < np) {
                     const int64_t g = gl[r];
                     s_gidx[l] = (uint32_t)g;
-                    s_q[l] = q[g];
-                    s_q[CP + l] = q[n + g];
-                    s_q[2 * CP + l] = q[2 * n + g];
                     s_p[l] = p[g];
                     s_p[CP + l] = p[n + g];
                     s_p[2 * CP + l] = p[2 * n + g];
                     s_eps[l] = eps[g];
-                    s_rho[l] = rho[g];
-                    s_id[l] = id[g];
                 }
             }
         }
@@ -244,24 +264,59 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                 }
             }
             __syncthreads();
+            // level steps: (level, first sorted position) in ascending order;
+            // the read-only data of step k + 1 is gathered before step k runs
             const int top = *s_maxlv;
-            for (int l = lo; l <= top; ++l) {
-                const int beg = (int)s_off[l], end = beg + (int)s_hist[l];
-                for (int b0 = beg; b0 < end; b0 += 64) {
-                    const int e = b0 + lane;
-                    if (e < end) {
-                        const uint32_t pr = s_sorted[e];
-                        int li = (int)(pr & 0xFFFFu), lj = (int)(pr >> 16);
-                        if (s_id[li] > s_id[lj]) {
-                            const int tt = li;
-                            li = lj;
-                            lj = tt;
-                        }
-                        fd_pair(P, step, dt, li, lj, s_q, s_p, CP, s_eps, s_rho, s_id, cnt,
-                                negeps);
+            int l = lo, b0 = (int)s_off[lo];
+            while (l <= top && b0 >= (int)(s_off[l] + s_hist[l])) {
+                ++l;
+                if (l <= top) b0 = (int)s_off[l];
+            }
+            PairGeo cur = {};
+            int cli = 0, clj = 0;
+            bool cval = false;
+            if (l <= top) {
+                const int e = b0 + lane;
+                cval = e < (int)(s_off[l] + s_hist[l]);
+                if (cval) fd_gather(s_sorted, s_gidx, q, rho, id, n, e, cli, clj, cur);
+            }
+            while (l <= top) {
+                int nl = l, nb = b0 + 64;
+                while (nl <= top && nb >= (int)(s_off[nl] + s_hist[nl])) {
+                    ++nl;
+                    if (nl <= top) nb = (int)s_off[nl];
+                }
+                PairGeo nxt = {};
+                int nli = 0, nlj = 0;
+                bool nval = false;
+                if (nl <= top) {
+                    const int e = nb + lane;
+                    nval = e < (int)(s_off[nl] + s_hist[nl]);
+                    if (nval) fd_gather(s_sorted, s_gidx, q, rho, id, n, e, nli, nlj, nxt);
+                }
+                if (cval) {
+                    if (cur.id_i > cur.id_j) {   // orient: i = smaller id
+                        const int tt = cli;
+                        cli = clj;
+                        clj = tt;
+                        double t;
+                        t = cur.xi; cur.xi = cur.xj; cur.xj = t;
+                        t = cur.yi; cur.yi = cur.yj; cur.yj = t;
+                        t = cur.zi; cur.zi = cur.zj; cur.zj = t;
+                        t = cur.rho_i; cur.rho_i = cur.rho_j; cur.rho_j = t;
+                        const uint32_t u = cur.id_i;
+                        cur.id_i = cur.id_j;
+                        cur.id_j = u;
                     }
+                    fd_pair(P, step, dt, cli, clj, cur, s_p, CP, s_eps, cnt, negeps);
                 }
                 __syncthreads();
+                cur = nxt;
+                cli = nli;
+                clj = nlj;
+                cval = nval;
+                l = nl;
+                b0 = nb;
             }
             lo = hi + 1;
             if (!oversized) break;
@@ -330,7 +385,7 @@ constexpr Allow kAllow[4] = {
     {14.7, 10.0, 25.2, 20.0},   // edge
     {6.7, 5.0, 5.4, 4.5},       // corner
 };
-constexpr int kDefaultTasks[4] = {8, 10, 24, 64};
+constexpr int kDefaultTasks[4] = {8, 8, 16, 48};
 
 int round_up(double x, int q)
 {

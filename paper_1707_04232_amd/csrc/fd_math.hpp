@@ -94,18 +94,24 @@ struct FdCount {
     uint32_t proposed, rej_energy, rej_ratio, marginal, negeps;
 };
 
-// One pair update on LDS-resident state; li has the smaller id.  s_q and s_p
-// hold the x, y, z planes at stride ps.
+// Read-only data of one pair (positions, densities, ids), gathered from
+// global memory one level step ahead of its use.
+struct PairGeo {
+    double xi, yi, zi, xj, yj, zj, rho_i, rho_j;
+    uint32_t id_i, id_j;
+};
+
+// One pair update; li has the smaller id.  Momenta (x, y, z planes at
+// stride ps) and energies are LDS-resident.
 __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, double dt, int li,
-                                        int lj, const double *s_q, double *s_p, int ps,
-                                        double *s_eps, const double *s_rho,
-                                        const uint32_t *s_id, FdCount &cnt, bool &negeps)
+                                        int lj, const PairGeo &g, double *s_p, int ps,
+                                        double *s_eps, FdCount &cnt, bool &negeps)
 {
 #pragma clang fp contract(fast)
     // geometry (Sec. 2.1.1): r_ij, e_ij, F_ij
-    const double dx = min_image(s_q[li] - s_q[lj], P.box[0], P.half_box[0]);
-    const double dy = min_image(s_q[ps + li] - s_q[ps + lj], P.box[1], P.half_box[1]);
-    const double dz = min_image(s_q[2 * ps + li] - s_q[2 * ps + lj], P.box[2], P.half_box[2]);
+    const double dx = min_image(g.xi - g.xj, P.box[0], P.half_box[0]);
+    const double dy = min_image(g.yi - g.yj, P.box[1], P.half_box[1]);
+    const double dz = min_image(g.zi - g.zj, P.box[2], P.half_box[2]);
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double inv_r = fast_rsq(r2);
     const double r = r2 * inv_r;
@@ -115,7 +121,7 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, doubl
     if (P.kernel == SDPD_KERNEL_LUCY) F = P.cF * (t * t);
     else F = x <= 0.5 ? P.cF * (2.0 - 3.0 * x) : P.cF * P.h * (t * t) * inv_r;
     // kappa^theta of Sec. 2.2.2
-    const double kfac = F * fast_rcp(s_rho[li] * s_rho[lj]);
+    const double kfac = F * fast_rcp(g.rho_i * g.rho_j);
     const double kpar = P.kpar_c * kfac, kperp = P.kperp_c * kfac;
 
     const double ei = s_eps[li], ej = s_eps[lj];
@@ -124,7 +130,7 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, doubl
     const double vz = (s_p[2 * ps + li] - s_p[2 * ps + lj]) * P.inv_m;
 
     double G[3], U;
-    pair_draws(P, step, s_id[li], s_id[lj], G, U);
+    pair_draws(P, step, g.id_i, g.id_j, G, U);
 
     // proposal, eq. (proposal): v' = A(v) v + B(v) G, B = (2/m) zeta^theta P^theta
     const Coef f = fd_coef(P, kpar, kperp, ei, ej, dt);
