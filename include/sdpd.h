@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SDPD_ABI_VERSION 1
+#define SDPD_ABI_VERSION 2
 
 typedef enum {
     SDPD_OK = 0,
@@ -180,9 +180,10 @@ int sdpd_sync(sdpd_ctx *ctx);
  * of the classes below is bracketed by two events.  sdpd_timing (sync)
  * returns, per class, the summed milliseconds and the number of launches
  * since the last call, then clears the record.  Classes: 0 cell build,
- * 1 density, 2 F/D phase kernels, 3 forces + half kick, 4 observables.     */
+ * 1 density, 2 F/D phase kernels, 3 forces + half kick, 4 observables,
+ * 5 F/D scheduling pass.                                                   */
 int sdpd_set_timing(sdpd_ctx *ctx, int enable);
-int sdpd_timing(sdpd_ctx *ctx, double ms[5], int64_t launches[5]);
+int sdpd_timing(sdpd_ctx *ctx, double ms[6], int64_t launches[6]);
 
 /* Execution-only tuning of the F/D sweep (results do not change).  Index k
  * is the phase class: 0 = phase 0 (pairs inside a cell), 1, 2, 3 = phases of

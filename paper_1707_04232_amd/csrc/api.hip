@@ -71,7 +71,7 @@ static int check_params(const sdpd_params *P, int nc[3])
         if (nc[k] < 0) return SDPD_EINVAL;
         ncell *= nc[k];
     }
-    if (ncell > 0x7fffffffLL) return SDPD_EINVAL;   // one workgroup per cell in a 1-D grid
+    if ((int64_t)NMASK * ncell > 0xffffffffLL) return SDPD_EINVAL;   // 32-bit task indices
     return SDPD_OK;
 }
 
@@ -373,9 +373,9 @@ int sdpd_step(sdpd_ctx *c, const sdpd_state *s, uint64_t step0, int nsteps, sdpd
             return rc;
         if ((rc = run_forces(c, s, 1))) return rc;
         if (per_step) {
-            timer_begin(c, TK_KICK);
+            timer_begin(c, TK_OBSERVE);
             rc = run_observe(c, s, c->obs_out + (size_t)k * REC);
-            timer_end(c, TK_KICK);
+            timer_end(c, TK_OBSERVE);
             if (rc) return rc;
         }
     }
@@ -422,7 +422,7 @@ int sdpd_set_timing(sdpd_ctx *c, int enable)
     return SDPD_OK;
 }
 
-int sdpd_timing(sdpd_ctx *c, double ms[5], int64_t launches[5])
+int sdpd_timing(sdpd_ctx *c, double ms[6], int64_t launches[6])
 {
     if (!c || !ms || !launches) return SDPD_EINVAL;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return SDPD_EHIP;

@@ -14,6 +14,8 @@
 //     Pairs of equal level in one task share no particle.
 // Pair entry (64 bits): the phase-relative list positions of its two
 // particles (25 bits each) and the level (bits 50..56).
+#include <type_traits>
+
 #include "fd_math.hpp"
 
 namespace sdpd {
@@ -30,28 +32,34 @@ __device__ __host__ __forceinline__ int64_t phase_base(int64_t ncell, int p)
     return p == 0 ? 0 : ncell + (int64_t)(p - 1) * (ncell / 8);
 }
 
-__device__ __forceinline__ TaskCells task_cells(const DevParams &P, int64_t T)
+// 32-bit index arithmetic throughout: 14 ncell < 2^32 is checked on the host
+// (64-bit division is a long software sequence on the GPU)
+__device__ __forceinline__ TaskCells task_cells(const DevParams &P, int64_t T64)
 {
     TaskCells r;
-    if (T < P.ncell) {
+    const uint32_t T = (uint32_t)T64, ncell = (uint32_t)P.ncell;
+    if (T < ncell) {
         r.A = r.B = T;
         r.slot = 0;
         r.phase = 0;
         return r;
     }
-    const int64_t per = P.ncell / 8;
-    const int p = 1 + (int)((T - P.ncell) / per);
-    const int64_t t = (T - P.ncell) % per;
+    const uint32_t per = ncell / 8u, u = T - ncell;
+    const uint32_t pq = u / per;
+    const uint32_t t = u - pq * per;
+    const int p = 1 + (int)pq;
     const int o = (p - 1) / 8, pi = (p - 1) % 8, k = 14 + o;
-    const int hx = P.nc[0] / 2, hy = P.nc[1] / 2;
-    const int tx = (int)(t % hx), ty = (int)((t / hx) % hy), tz = (int)(t / ((int64_t)hx * hy));
-    const int ax = 2 * tx + (pi & 1), ay = 2 * ty + ((pi >> 1) & 1), az = 2 * tz + (pi >> 2);
+    const uint32_t hx = (uint32_t)P.nc[0] / 2u, hy = (uint32_t)P.nc[1] / 2u;
+    const uint32_t txy = t / hx, tx = t - txy * hx;
+    const uint32_t tz = txy / hy, ty = txy - tz * hy;
+    const int ax = 2 * (int)tx + (pi & 1), ay = 2 * (int)ty + ((pi >> 1) & 1),
+              az = 2 * (int)tz + (pi >> 2);
     int bx = ax + k % 3 - 1, by = ay + (k / 3) % 3 - 1, bz = az + k / 9 - 1;
     bx += bx >= P.nc[0] ? -P.nc[0] : (bx < 0 ? P.nc[0] : 0);
     by += by >= P.nc[1] ? -P.nc[1] : (by < 0 ? P.nc[1] : 0);
     bz += bz >= P.nc[2] ? -P.nc[2] : (bz < 0 ? P.nc[2] : 0);
-    r.A = ax + (int64_t)P.nc[0] * (ay + (int64_t)P.nc[1] * az);
-    r.B = bx + (int64_t)P.nc[0] * (by + (int64_t)P.nc[1] * bz);
+    r.A = (uint32_t)ax + (uint32_t)P.nc[0] * ((uint32_t)ay + (uint32_t)P.nc[1] * (uint32_t)az);
+    r.B = (uint32_t)bx + (uint32_t)P.nc[0] * ((uint32_t)by + (uint32_t)P.nc[1] * (uint32_t)bz);
     r.slot = o + 1;
     r.phase = p;
     return r;
@@ -82,8 +90,126 @@ __global__ void k_task_count(const DevParams *__restrict__ Pp,
     tnp[T] = na + (tc.slot == 0 ? 0u : (uint32_t)__popcll(orb));
 }
 
-// levels, particle lists and pair entries: one wave per task (grid-stride)
-__global__ __launch_bounds__(64) void k_schedule(const DevParams *__restrict__ Pp,
+struct TaskSpan {
+    TaskCells tc;
+    uint32_t sA, nA, sB, nB, e0, e1, q0, q1, rel;
+};
+
+__device__ __forceinline__ TaskSpan task_span(const DevParams &P, const uint32_t *cell_start,
+                                              const uint32_t *pair_off, const uint32_t *part_off,
+                                              int64_t T)
+{
+    TaskSpan t;
+    t.tc = task_cells(P, T);
+    t.sA = cell_start[t.tc.A];
+    t.nA = cell_start[t.tc.A + 1] - t.sA;
+    t.sB = cell_start[t.tc.B];
+    t.nB = cell_start[t.tc.B + 1] - t.sB;
+    t.e0 = pair_off[T];
+    t.e1 = pair_off[T + 1];
+    t.q0 = part_off[T];
+    t.q1 = part_off[T + 1];
+    t.rel = t.q0 - part_off[phase_base(P.ncell, t.tc.phase)];
+    return t;
+}
+
+// OR over the lanes of one W-lane segment
+template <int W>
+__device__ __forceinline__ uint64_t seg_or64(uint64_t v)
+{
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) {
+        lo |= (uint32_t)__shfl_xor((int)lo, off);
+        hi |= (uint32_t)__shfl_xor((int)hi, off);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// One task on a W-lane segment of the wave (W = 64: the whole wave; W = 32:
+// one half, for cells of at most 32 particles, so that every slot and every
+// round partner x ^ s lies in the half).  Lane x of the segment is slot x of
+// cell A and of cell B.  Writes the task's particle list and its pairs in
+// round order with their levels.  `ok` = this segment has a task to do;
+// `intra` is the same for the whole wave (tasks of one pair never mix phase
+// 0 with the others, since ncell is even).
+template <int W>
+__device__ __forceinline__ void schedule_segment(const DevParams &P, const TaskSpan &t, bool ok,
+                                                 bool intra,
+                                                 const uint64_t *__restrict__ masks,
+                                                 uint64_t *pairs, uint32_t *part_list)
+{
+    using M = typename std::conditional<W == 32, uint32_t, uint64_t>::type;
+    const int lane = threadIdx.x & 63;
+    const int base = lane & ~(W - 1), x = lane & (W - 1);
+    const bool hi = base != 0;
+    const M below = (M)(((uint64_t)1 << x) - 1u);   // x < W <= 64
+    const uint64_t mask64 = ok && (uint32_t)x < t.nA
+                                ? masks[(int64_t)(OWN_NB + t.tc.slot) * P.n + t.sA + x] : 0ull;
+    const M mask = (M)mask64;   // W = 32: partner slots < 32
+    const uint64_t bact = __ballot(mask != 0);
+    const M actA = (M)(hi ? (bact >> 32) : bact);
+    const M actB = intra ? actA : (M)seg_or64<W>(mask);
+    const uint32_t nactA = (uint32_t)__popcll(actA);
+    // particle list: A-side participants by slot, then (inter-cell) B-side
+    if ((actA >> x) & 1u) part_list[t.q0 + __popcll(actA & below)] = t.sA + (uint32_t)x;
+    if (!intra && ((actB >> x) & 1u))
+        part_list[t.q0 + nactA + __popcll(actB & below)] = t.sB + (uint32_t)x;
+    // phase-relative list positions of this lane as A-side and as B-side particle
+    const uint32_t posA = t.rel + (uint32_t)__popcll(actA & below);
+    const uint32_t posB = intra ? posA : t.rel + nactA + (uint32_t)__popcll(actB & below);
+    const M rm = (M)xor_permute_bits(mask, (uint32_t)x);   // bit s: partner x ^ s active
+    uint64_t r = seg_or64<W>(rm);
+    if (W == 32) r |= (uint32_t)__shfl_xor((int)(uint32_t)r, 32);   // union of the halves
+    uint64_t rounds = uniform64(r);
+    int LA = 0, LB = 0;
+    uint32_t pos = t.e0;
+    while (rounds) {
+        const int s = __builtin_ctzll(rounds);   // uniform
+        rounds &= rounds - 1;
+        const int partner = x ^ s;                // < W
+        const int addr = (base + partner) << 2;   // byte address of the partner lane
+        const bool act = (rm >> s) & 1u;
+        const int la = __builtin_amdgcn_ds_bpermute(addr, LA);
+        const int lb = __builtin_amdgcn_ds_bpermute(addr, LB);
+        const bool actB_here = __builtin_amdgcn_ds_bpermute(addr, (int)act) != 0;
+        const uint32_t pB = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)posB);
+        bool own;
+        if (intra) {
+            own = act && x < partner;
+            if (act) LA = (LA > la ? LA : la) + 1;
+        } else {
+            own = act;
+            if (act) LA = (LA > lb ? LA : lb) + 1;
+            if (actB_here) LB = (LB > la ? LB : la) + 1;
+        }
+        const uint64_t bal = __ballot(own);
+        const uint32_t blo = (uint32_t)bal, bhi = (uint32_t)(bal >> 32);
+        if (own) {
+            // rank among the owning lanes of this segment
+            uint32_t k = __builtin_amdgcn_mbcnt_hi(bhi, __builtin_amdgcn_mbcnt_lo(blo, 0u));
+            if (W == 32 && hi) k -= (uint32_t)__popc(blo);
+            const uint64_t e = (uint64_t)posA | ((uint64_t)pB << 25) | ((uint64_t)LA << 50);
+            pairs[pos + k] = e;
+        }
+        pos += W == 32 ? (uint32_t)__popc(hi ? bhi : blo) : (uint32_t)__popcll(bal);
+    }
+}
+
+// levels, particle lists and pair entries (grid-stride over pairs of
+// consecutive tasks; 14 * ncell is even).  Both tasks of a pair run side by
+// side in the two halves of the wave when all their cells hold at most 32
+// particles, otherwise one after the other on the whole wave.
+constexpr int SCHED_WAVES = 4;   // waves per workgroup, each on its own task pairs
+
+__global__ __launch_bounds__(64 * SCHED_WAVES) void k_schedule(const DevParams *__restrict__ Pp,
                                                  const uint32_t *__restrict__ cell_start,
                                                  const uint64_t *__restrict__ masks,
                                                  const uint32_t *__restrict__ pair_off,
@@ -93,60 +219,36 @@ __global__ __launch_bounds__(64) void k_schedule(const DevParams *__restrict__ P
                                                  uint32_t *err)
 {
     const DevParams &P = *Pp;
-    const int lane = threadIdx.x;
     const int64_t ntask = (int64_t)NMASK * P.ncell;
-    for (int64_t T = blockIdx.x; T < ntask; T += gridDim.x) {
-        const TaskCells tc = task_cells(P, T);
-        const bool intra = tc.slot == 0;
-        const uint32_t sA = cell_start[tc.A], nA = cell_start[tc.A + 1] - sA;
-        const uint32_t sB = cell_start[tc.B], nB = cell_start[tc.B + 1] - sB;
-        const uint32_t e0 = pair_off[T], e1 = pair_off[T + 1];
-        const uint32_t q0 = part_off[T], q1 = part_off[T + 1];
-        if (e1 == e0) continue;
-        if (nA > (uint32_t)P.cap || nB > (uint32_t)P.cap || e1 > pair_cap || q1 > part_cap) {
+    // wave index made explicitly uniform: the task arithmetic below then runs
+    // on the scalar unit once per wave
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    for (int64_t Wp = (int64_t)blockIdx.x * SCHED_WAVES + wave; 2 * Wp < ntask;
+         Wp += (int64_t)gridDim.x * SCHED_WAVES) {
+        const TaskSpan ta = task_span(P, cell_start, pair_off, part_off, 2 * Wp);
+        const TaskSpan tb = task_span(P, cell_start, pair_off, part_off, 2 * Wp + 1);
+        bool oka = ta.e1 > ta.e0, okb = tb.e1 > tb.e0;
+        const bool bada = oka && (ta.nA > (uint32_t)P.cap || ta.nB > (uint32_t)P.cap ||
+                                  ta.e1 > pair_cap || ta.q1 > part_cap);
+        const bool badb = okb && (tb.nA > (uint32_t)P.cap || tb.nB > (uint32_t)P.cap ||
+                                  tb.e1 > pair_cap || tb.q1 > part_cap);
+        if (bada || badb) {
             if (lane == 0) atomicOr(err, ERR_PAIRCAP);
-            continue;
+            oka = oka && !bada;
+            okb = okb && !badb;
         }
-        const uint64_t mask =
-            (uint32_t)lane < nA ? masks[(int64_t)(OWN_NB + tc.slot) * P.n + sA + lane] : 0ull;
-        const uint64_t actA = __ballot(mask != 0ull);
-        const uint64_t actB = intra ? actA : wave_or64(mask);
-        const uint32_t nactA = (uint32_t)__popcll(actA);
-        const uint32_t rel = q0 - part_off[phase_base(P.ncell, tc.phase)];
-        // particle list
-        if ((actA >> lane) & 1ull)
-            part_list[q0 + __popcll(actA & ((1ull << lane) - 1ull))] = sA + (uint32_t)lane;
-        if (!intra && ((actB >> lane) & 1ull))
-            part_list[q0 + nactA + __popcll(actB & ((1ull << lane) - 1ull))] = sB + (uint32_t)lane;
-        // list positions of this lane as A-side and as B-side particle
-        const uint64_t posA = rel + (uint32_t)__popcll(actA & ((1ull << lane) - 1ull));
-        const uint64_t posB = intra ? posA
-                                    : rel + nactA + (uint32_t)__popcll(actB & ((1ull << lane) - 1ull));
-        const uint64_t rm = xor_permute_bits(mask, (uint32_t)lane);
-        uint64_t rounds = wave_or64(rm);
-        int LA = 0, LB = 0;
-        uint32_t pos = e0;
-        while (rounds) {
-            const int s = __builtin_ctzll(rounds);
-            rounds &= rounds - 1;
-            const int partner = lane ^ s;
-            const bool act = (rm >> s) & 1ull;
-            const int la = __shfl(LA, partner), lb = __shfl(LB, partner);
-            const bool actB_here = __shfl((int)act, partner) != 0;
-            const uint64_t pB = (uint64_t)(uint32_t)__shfl((int)(uint32_t)posB, partner);
-            const bool own = intra ? (act && lane < partner) : act;
-            if (intra) {
-                if (act) LA = (LA > la ? LA : la) + 1;
-            } else {
-                if (act) LA = (LA > lb ? LA : lb) + 1;
-                if (actB_here) LB = (LB > la ? LB : la) + 1;
-            }
-            const uint64_t bal = __ballot(own);
-            if (own) {
-                const uint32_t k = pos + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-                pairs[k] = posA | (pB << 25) | ((uint64_t)LA << 50);
-            }
-            pos += (uint32_t)__popcll(bal);
+        if (!oka && !okb) continue;
+        uint32_t widest = 0;
+        if (oka) widest = max(ta.nA, ta.nB);
+        if (okb) widest = max(widest, max(tb.nA, tb.nB));
+        if (widest <= 32) {
+            const bool hi = lane >= 32;
+            const TaskSpan t = hi ? tb : ta;   // field-wise select
+            schedule_segment<32>(P, t, hi ? okb : oka, ta.tc.slot == 0, masks, pairs, part_list);
+        } else {
+            if (oka) schedule_segment<64>(P, ta, true, ta.tc.slot == 0, masks, pairs, part_list);
+            if (okb) schedule_segment<64>(P, tb, true, tb.tc.slot == 0, masks, pairs, part_list);
         }
     }
 }
@@ -154,18 +256,23 @@ __global__ __launch_bounds__(64) void k_schedule(const DevParams *__restrict__ P
 int run_schedule(sdpd_ctx *c)
 {
     const int64_t ntask = (int64_t)NMASK * c->ncell;
+    timer_begin(c, TK_SCHED);
     hipLaunchKernelGGL(k_task_count, dim3((unsigned)((ntask + 255) / 256)), dim3(256), 0, c->stream,
                        c->dparams, c->cell_start, c->masks, c->task_count, c->task_np);
     int rc = check_hip(hipGetLastError());
     if (rc) return rc;
     if ((rc = run_scan(c, c->task_count, c->pair_off, ntask, c->block_sums, -1))) return rc;
     if ((rc = run_scan(c, c->task_np, c->part_off, ntask, c->block_sums, -1))) return rc;
-    // one workgroup per task: many independent short tasks hide the load latency
-    const int64_t grid = std::min<int64_t>(ntask, 0x7fffffffLL);
-    hipLaunchKernelGGL(k_schedule, dim3((unsigned)grid), dim3(64), 0, c->stream, c->dparams,
+    // one workgroup per pair of tasks: many independent short waves hide the
+    // load latency
+    const int64_t grid = std::min<int64_t>((ntask / 2 + SCHED_WAVES - 1) / SCHED_WAVES, 0x7fffffffLL);
+    hipLaunchKernelGGL(k_schedule, dim3((unsigned)grid), dim3(64 * SCHED_WAVES), 0, c->stream,
+                       c->dparams,
                        c->cell_start, c->masks, c->pair_off, c->part_off, c->pairs, c->part_list,
                        (uint32_t)c->pair_cap, (uint32_t)c->part_cap, c->err);
-    return check_hip(hipGetLastError());
+    rc = check_hip(hipGetLastError());
+    timer_end(c, TK_SCHED);
+    return rc;
 }
 
 }  // namespace sdpd

@@ -54,7 +54,7 @@ struct DevParams {
 constexpr int REC = 12;
 
 // kernel timing classes
-enum { TK_CELLS = 0, TK_DENSITY, TK_FD, TK_FORCE, TK_KICK, TK_N };
+enum { TK_CELLS = 0, TK_DENSITY, TK_FD, TK_FORCE, TK_OBSERVE, TK_SCHED, TK_N };
 
 struct Timer {
     std::vector<hipEvent_t> pool;

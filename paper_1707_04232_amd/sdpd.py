@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_PKG, "libsdpd.so")
 OK, EINVAL, EHIP, ENOMEM, ECELLCAP, ENEGEPS, ENONFINITE, ECAPACITY = 0, -1, -2, -3, -4, -5, -6, -7
 KERNEL_LUCY, KERNEL_CUBIC = 0, 1
 FD_EMS, FD_AMS, FD_SSA, FD_NONE = 0, 1, 2, 3
-TIMING_CLASSES = ("cells", "density", "fd", "forces", "observe")
+TIMING_CLASSES = ("cells", "density", "fd", "forces", "observe", "schedule")
 
 EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
            "sdpd_copy_cell_start", "sdpd_density",
@@ -252,8 +252,8 @@ class Context:
         _check(lib().sdpd_set_timing(self._h, int(bool(enable))), "sdpd_set_timing")
 
     def timing(self) -> dict:
-        ms = (C.c_double * 5)()
-        cnt = (C.c_int64 * 5)()
+        ms = (C.c_double * len(TIMING_CLASSES))()
+        cnt = (C.c_int64 * len(TIMING_CLASSES))()
         _check(lib().sdpd_timing(self._h, ms, cnt), "sdpd_timing")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(TIMING_CLASSES)}
 
