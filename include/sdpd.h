@@ -194,7 +194,7 @@ int sdpd_timing(sdpd_ctx *ctx, double ms[6], int64_t launches[6]);
  *   fd_lds_pairs[k]      pair entries one workgroup sorts in LDS, >= 64.
  * A workgroup whose tasks need more than its capacity processes them in
  * several batches.  The LDS of one workgroup, 36 B per particle + 4 B per
- * pair entry + 1316 B, must fit the device's per-workgroup limit.  Fields
+ * pair entry + 1320 B, must fit the device's per-workgroup limit.  Fields
  * equal to 0 in sdpd_tune keep the current value; sdpd_get_tuning reports
  * the values in use (the defaults scale with the mean particles per cell).
  * SDPD_EINVAL for out-of-range values; nothing is changed then.          */

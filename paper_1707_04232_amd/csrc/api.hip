@@ -138,7 +138,7 @@ static void free_ctx(sdpd_ctx *c)
                     c->perm, c->cell_sorted, c->tq, c->tp, c->teps, c->trho, c->tf, c->tid,
                     c->pi, c->masks, c->counters, c->err, c->obs_partial, c->obs_out,
                     c->dparams, c->task_count, c->task_np, c->pair_off, c->part_off,
-                    c->part_list, c->pairs};
+                    c->part_list, c->pairs, c->draws};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
@@ -281,6 +281,7 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     rc = rc ? rc : dalloc(&c->pair_off, (size_t)NMASK * nce + 1);
     rc = rc ? rc : dalloc(&c->part_off, (size_t)NMASK * nce + 1);
     rc = rc ? rc : dalloc(&c->pairs, (size_t)c->pair_cap);
+    rc = rc ? rc : dalloc(&c->draws, (size_t)4 * c->pair_cap);
     rc = rc ? rc : dalloc(&c->part_list, (size_t)c->part_cap);
     if (!rc)
         rc = check_hip(hipMemcpyAsync(c->dparams, &c->dp, sizeof c->dp, hipMemcpyHostToDevice,

@@ -21,7 +21,11 @@
 // particle) as parallel steps of 64 lanes.  Positions, densities and ids do
 // not change during the sweep: they are read from global memory, one level
 // step ahead of their use, which keeps the LDS footprint at 36 B per
-// particle and leaves room for more resident waves.
+// particle and leaves room for more resident waves.  The random draws of a
+// pair depend only on (step, ids): after the level sort they are computed for
+// all of the batch's pairs at full lane occupancy (which also orients every
+// pair, i = smaller id) and stored in sorted order in a global buffer, from
+// which the level steps prefetch them with the positions.
 //
 // Phases that touch disjoint cells commute.  Phase 1 + 8 o + pi touches the
 // cells of parity pi (as A) and pi ^ b_o (as B = A + delta_o, b_o the parity
@@ -58,15 +62,18 @@ struct FdLaunch {
 // sorted[cap_e] and the small tables (32-bit)
 __host__ __device__ inline size_t fd_lds_bytes(int cap_p, int cap_e)
 {
-    return (size_t)36 * cap_p + (size_t)4 * cap_e + 4 * (3 * (FD_NLVL + 2) + 2 * (FD_MAXTASKS + 1) + 1);
+    return (size_t)36 * cap_p + (size_t)4 * cap_e + 4 * (3 * (FD_NLVL + 2) + 2 * (FD_MAXTASKS + 1) + 2);
 }
 
-// read-only data of the pair at sorted position e (batch particle indices
-// li, lj from the LDS list); loads are issued, not waited for
+constexpr uint64_t POS_MASK = (1ull << 25) - 1ull;   // list position field of a pair entry
+
+// read-only data of the (oriented) pair at sorted position e: batch particle
+// indices from the LDS list, then positions, densities and the stored draws;
+// loads are issued, not waited for
 __device__ __forceinline__ void fd_gather(const uint32_t *s_sorted, const uint32_t *s_gidx,
                                           const double *__restrict__ q,
                                           const double *__restrict__ rho,
-                                          const uint32_t *__restrict__ id, int64_t n, int e,
+                                          const double *__restrict__ draws, int64_t n, int e,
                                           int &li, int &lj, PairGeo &g)
 {
     const uint32_t pr = s_sorted[e];
@@ -81,11 +88,13 @@ __device__ __forceinline__ void fd_gather(const uint32_t *s_sorted, const uint32
     g.zj = q[2 * n + gj];
     g.rho_i = rho[gi];
     g.rho_j = rho[gj];
-    g.id_i = id[gi];
-    g.id_j = id[gj];
+    const double2 *d = reinterpret_cast<const double2 *>(draws) + 2 * (int64_t)e;
+    const double2 d01 = d[0], d23 = d[1];
+    g.G0 = d01.x;
+    g.G1 = d01.y;
+    g.G2 = d23.x;
+    g.lnU = d23.y;
 }
-
-constexpr uint64_t POS_MASK = (1ull << 25) - 1ull;
 
 __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ Pp, FdLaunch L,
                                                  const double *__restrict__ q, double *p,
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                                                  const uint64_t *__restrict__ pairs,
                                                  const uint32_t *__restrict__ part_list,
                                                  uint32_t pair_cap, uint32_t part_cap,
-                                                 uint32_t step, double dt,
+                                                 uint32_t step, double dt, double *draws,
                                                  unsigned long long *counters, uint32_t *err)
 {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -111,6 +120,7 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
     uint32_t *s_eoff = s_cur + (FD_NLVL + 2);        // pair-entry offsets of the range's tasks
     uint32_t *s_poff = s_eoff + (FD_MAXTASKS + 1);   // particle-list offsets
     int *s_maxlv = (int *)(s_poff + (FD_MAXTASKS + 1));
+    int *s_ntot = s_maxlv + 1;                        // sorted entries of the window
 
     const DevParams &P = *Pp;
     const int lane = threadIdx.x;
@@ -223,8 +233,13 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                 }
 #pragma unroll
                 for (int r = 0; r < FD_EPL; ++r) {
-                    const int lv = (int)(ebuf[r] >> 50);
-                    if (lv >= lo && lv <= hi && lv <= FD_NLVL) atomicAdd(&s_hist[lv], 1u);
+                    const uint64_t e = ebuf[r];
+                    const int lv = (int)(e >> 50);
+                    const int li = (int)((uint32_t)(e & POS_MASK) - rel0);
+                    const int lj = (int)((uint32_t)((e >> 25) & POS_MASK) - rel0);
+                    if (lv >= lo && lv <= hi && lv <= FD_NLVL && li >= 0 && li < np && lj >= 0 &&
+                        lj < np)
+                        atomicAdd(&s_hist[lv], 1u);
                 }
             }
             __syncthreads();
@@ -240,6 +255,7 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                 s_cur[lane + 1] = incl - h;
                 const uint64_t nz = __ballot(h != 0u);
                 if (lane == 0) *s_maxlv = nz ? 64 - __clzll(nz) : 0;
+                if (lane == 63) *s_ntot = (int)incl;
             }
             __syncthreads();
             for (int base = 0; base < npr; base += EP) {
@@ -264,9 +280,46 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                 }
             }
             __syncthreads();
+            // draws of the window's pairs in sorted order, all lanes busy; the
+            // ids also orient each entry (A side = smaller id)
+            {
+                const int ntot = min(*s_ntot, CE);
+                double *wdraws = draws + 4 * (int64_t)e_begin;
+                constexpr int DPL = 4;   // entries per lane per pass: id loads in flight
+                for (int base = 0; base < ntot; base += DPL * 64) {
+                    uint32_t pr[DPL], ida[DPL], idb[DPL];
+#pragma unroll
+                    for (int r = 0; r < DPL; ++r) {
+                        const int e = base + r * 64 + lane;
+                        pr[r] = e < ntot ? s_sorted[e] : 0u;
+                        ida[r] = e < ntot ? id[s_gidx[pr[r] & 0xFFFFu]] : 0u;
+                        idb[r] = e < ntot ? id[s_gidx[pr[r] >> 16]] : 0u;
+                    }
+#pragma unroll
+                    for (int r = 0; r < DPL; ++r) {
+                        const int e = base + r * 64 + lane;
+                        if (e < ntot) {
+                            uint32_t i0 = ida[r], i1 = idb[r];
+                            if (i0 > i1) {
+                                s_sorted[e] = (pr[r] >> 16) | (pr[r] << 16);
+                                const uint32_t t = i0;
+                                i0 = i1;
+                                i1 = t;
+                            }
+                            double d[4];
+                            pair_draws_log(P, step, i0, i1, d);
+                            double2 *dst = reinterpret_cast<double2 *>(wdraws) + 2 * (int64_t)e;
+                            dst[0] = make_double2(d[0], d[1]);
+                            dst[1] = make_double2(d[2], d[3]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
             // level steps: (level, first sorted position) in ascending order;
             // the read-only data of step k + 1 is gathered before step k runs
             const int top = *s_maxlv;
+            const double *wdr = draws + 4 * (int64_t)e_begin;
             int l = lo, b0 = (int)s_off[lo];
             while (l <= top && b0 >= (int)(s_off[l] + s_hist[l])) {
                 ++l;
@@ -278,7 +331,7 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
             if (l <= top) {
                 const int e = b0 + lane;
                 cval = e < (int)(s_off[l] + s_hist[l]);
-                if (cval) fd_gather(s_sorted, s_gidx, q, rho, id, n, e, cli, clj, cur);
+                if (cval) fd_gather(s_sorted, s_gidx, q, rho, wdr, n, e, cli, clj, cur);
             }
             while (l <= top) {
                 int nl = l, nb = b0 + 64;
@@ -292,24 +345,9 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                 if (nl <= top) {
                     const int e = nb + lane;
                     nval = e < (int)(s_off[nl] + s_hist[nl]);
-                    if (nval) fd_gather(s_sorted, s_gidx, q, rho, id, n, e, nli, nlj, nxt);
+                    if (nval) fd_gather(s_sorted, s_gidx, q, rho, wdr, n, e, nli, nlj, nxt);
                 }
-                if (cval) {
-                    if (cur.id_i > cur.id_j) {   // orient: i = smaller id
-                        const int tt = cli;
-                        cli = clj;
-                        clj = tt;
-                        double t;
-                        t = cur.xi; cur.xi = cur.xj; cur.xj = t;
-                        t = cur.yi; cur.yi = cur.yj; cur.yj = t;
-                        t = cur.zi; cur.zi = cur.zj; cur.zj = t;
-                        t = cur.rho_i; cur.rho_i = cur.rho_j; cur.rho_j = t;
-                        const uint32_t u = cur.id_i;
-                        cur.id_i = cur.id_j;
-                        cur.id_j = u;
-                    }
-                    fd_pair(P, step, dt, cli, clj, cur, s_p, CP, s_eps, cnt, negeps);
-                }
+                if (cval) fd_pair(P, dt, cli, clj, cur, s_p, CP, s_eps, cnt, negeps);
                 __syncthreads();
                 cur = nxt;
                 cli = nli;
@@ -469,7 +507,7 @@ static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, in
     hipLaunchKernelGGL(k_fd_phase, dim3((unsigned)wg), dim3(64), lds, c->stream, c->dparams, L,
                        s->q, s->p, s->eps, s->rho, s->id, c->pair_off, c->part_off, c->pairs,
                        c->part_list, (uint32_t)c->pair_cap, (uint32_t)c->part_cap,
-                       (uint32_t)step, dt_fd, c->counters, c->err);
+                       (uint32_t)step, dt_fd, c->draws, c->counters, c->err);
     timer_end(c, TK_FD);
     return check_hip(hipGetLastError());
 }

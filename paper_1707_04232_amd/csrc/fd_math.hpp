@@ -94,24 +94,37 @@ struct FdCount {
     uint32_t proposed, rej_energy, rej_ratio, marginal, negeps;
 };
 
-// Read-only data of one pair (positions, densities, ids), gathered from
-// global memory one level step ahead of its use.
+// Read-only data of one oriented pair (i = smaller id): positions,
+// densities and its random draws (Gaussian vector and log of the uniform),
+// gathered from global memory one level step ahead of its use.
 struct PairGeo {
     double xi, yi, zi, xj, yj, zj, rho_i, rho_j;
-    uint32_t id_i, id_j;
+    double G0, G1, G2, lnU;
 };
+
+// The draws of the pair (id_i < id_j) as stored for the sweep: G1, G2, G3, ln U
+__device__ __forceinline__ void pair_draws_log(const DevParams &P, uint32_t step, uint32_t id_i,
+                                               uint32_t id_j, double out[4])
+{
+    double G[3], U;
+    pair_draws(P, step, id_i, id_j, G, U);
+    out[0] = G[0];
+    out[1] = G[1];
+    out[2] = G[2];
+    out[3] = fd_log(U);
+}
 
 // One pair update; li has the smaller id.  Momenta (x, y, z planes at
 // stride ps) and energies are LDS-resident.
-__device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, double dt, int li,
-                                        int lj, const PairGeo &g, double *s_p, int ps,
+__device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
+                                        int lj, const PairGeo &pg, double *s_p, int ps,
                                         double *s_eps, FdCount &cnt, bool &negeps)
 {
 #pragma clang fp contract(fast)
     // geometry (Sec. 2.1.1): r_ij, e_ij, F_ij
-    const double dx = min_image(g.xi - g.xj, P.box[0], P.half_box[0]);
-    const double dy = min_image(g.yi - g.yj, P.box[1], P.half_box[1]);
-    const double dz = min_image(g.zi - g.zj, P.box[2], P.half_box[2]);
+    const double dx = min_image(pg.xi - pg.xj, P.box[0], P.half_box[0]);
+    const double dy = min_image(pg.yi - pg.yj, P.box[1], P.half_box[1]);
+    const double dz = min_image(pg.zi - pg.zj, P.box[2], P.half_box[2]);
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double inv_r = fast_rsq(r2);
     const double r = r2 * inv_r;
@@ -121,7 +134,7 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, doubl
     if (P.kernel == SDPD_KERNEL_LUCY) F = P.cF * (t * t);
     else F = x <= 0.5 ? P.cF * (2.0 - 3.0 * x) : P.cF * P.h * (t * t) * inv_r;
     // kappa^theta of Sec. 2.2.2
-    const double kfac = F * fast_rcp(g.rho_i * g.rho_j);
+    const double kfac = F * fast_rcp(pg.rho_i * pg.rho_j);
     const double kpar = P.kpar_c * kfac, kperp = P.kperp_c * kfac;
 
     const double ei = s_eps[li], ej = s_eps[lj];
@@ -129,8 +142,7 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, doubl
     const double vy = (s_p[ps + li] - s_p[ps + lj]) * P.inv_m;
     const double vz = (s_p[2 * ps + li] - s_p[2 * ps + lj]) * P.inv_m;
 
-    double G[3], U;
-    pair_draws(P, step, g.id_i, g.id_j, G, U);
+    const double G[3] = {pg.G0, pg.G1, pg.G2};
 
     // proposal, eq. (proposal): v' = A(v) v + B(v) G, B = (2/m) zeta^theta P^theta
     const Coef f = fd_coef(P, kpar, kperp, ei, ej, dt);
@@ -180,7 +192,7 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, uint32_t step, doubl
             const double ui = -delta * ej * inv_eiej, uj = -delta * ei * inv_eiej;
             const double ent = P.ent_c * fd_log1p(ui + uj + ui * uj);
             const double a = 0.5 * G2 - 0.5 * quad + logdet + ent;
-            const double lnU = fd_log(U);
+            const double lnU = pg.lnU;
             if (fabs(a - lnU) <= 1e-9) cnt.marginal += 1;
             if (!(lnU <= a)) {                       // reject iff U > exp(a)
                 accept = false;

@@ -91,6 +91,7 @@ struct sdpd_ctx {
     // pair schedule (rebuilt before every sweep)
     uint32_t *task_count, *task_np, *pair_off, *part_off, *part_list;
     uint64_t *pairs;
+    double *draws;               // 4 per pair entry: the sweep's random draws in sorted order
     int64_t pair_cap, part_cap;
     sdpd::Timer timer;
     int timing;
