@@ -31,6 +31,11 @@ HBM_PEAK_GBS = 8000.0
 # by the FP64 operations of its gfx950 implementation (46, 63, 38, 16, 9, 10
 # and 43 flops): 209 + 564 = 773.
 FLOPS_PER_EMS_PAIR = 773.0
+# compulsory HBM bytes of the F/D phase kernel: per staged particle entry its
+# list entry (4), p and eps read and written (64), q, rho, id read (36); per
+# pair its schedule entry (8)
+BYTES_PER_STAGED = 104.0
+BYTES_PER_PAIR_ENTRY = 8.0
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "fd_phase_traffic.json")
 FD_SOURCES = ["fd.hip", "fd_math.hpp", "fd_elem.hpp", "schedule.hip", "sdpd_internal.hpp"]
 
@@ -138,6 +143,7 @@ def main():
     tm = ctx.timing()
     ctx.set_timing(False)
     ctx.sync()
+    last_pairs, last_staged = ctx.fd_schedule_size()
     elapsed = t1 - t0
     value = w.n * args.steps / elapsed
 
@@ -156,11 +162,16 @@ def main():
         avg_ms = fd_ms / fd_launches
         flops_per_launch = FLOPS_PER_EMS_PAIR * proposed / fd_launches
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        launches_per_sweep = fd_launches / args.steps
+        alg_bytes = (last_staged * BYTES_PER_STAGED + last_pairs * BYTES_PER_PAIR_ENTRY) \
+            / launches_per_sweep
         roof = {"bound": "alu", "kernel": "k_fd_phase", "achieved": achieved,
                 "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": measured_traffic(),
+                "algorithmic_bytes_per_launch": alg_bytes,
                 "avg_launch_ms": avg_ms, "launches": fd_launches,
-                "pairs_per_launch": proposed / fd_launches}
+                "pairs_per_launch": proposed / fd_launches,
+                "flops_per_pair": FLOPS_PER_EMS_PAIR}
     breakdown = {k: {"ms_per_step": v[0] / args.steps, "launches": v[1]}
                  for k, v in tm.items()}
 
@@ -180,6 +191,7 @@ def main():
                    "fd": "EMS", "steps": args.steps},
         "energy_drift": drift,
         "fd": {"pairs_per_step": proposed / args.steps,
+               "staged_per_step_last": last_staged,
                "rejection_rate": (rej_e + rej_r) / max(proposed, 1),
                "rej_energy": rej_e, "rej_ratio": rej_r},
         "kernel_ms_per_step": breakdown,

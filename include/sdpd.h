@@ -207,6 +207,12 @@ typedef struct {
 int sdpd_tune(sdpd_ctx *ctx, const sdpd_tuning *tuning);
 int sdpd_get_tuning(sdpd_ctx *ctx, sdpd_tuning *out);
 
+/* Size of the pair schedule of the last F/D sweep (sync): the number of
+ * active pairs and the number of particle entries the phase workgroups
+ * staged (a particle counts once per task it takes part in).  Zeros before
+ * the first sweep.                                                          */
+int sdpd_fd_schedule_size(sdpd_ctx *ctx, int64_t *pairs, int64_t *staged);
+
 const char *sdpd_strerror(int status);
 int sdpd_abi_version(void);
 

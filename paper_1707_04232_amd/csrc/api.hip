@@ -457,6 +457,25 @@ int sdpd_tune(sdpd_ctx *c, const sdpd_tuning *t)
     return SDPD_OK;
 }
 
+int sdpd_fd_schedule_size(sdpd_ctx *c, int64_t *pairs, int64_t *staged)
+{
+    if (!c || !pairs || !staged) return SDPD_EINVAL;
+    *pairs = *staged = 0;
+    if (!c->fd_swept) return SDPD_OK;
+    const int64_t ntask = (int64_t)NMASK * c->ncell;
+    uint32_t v[2] = {0u, 0u};
+    int rc = check_hip(hipMemcpyAsync(&v[0], c->pair_off + ntask, sizeof(uint32_t),
+                                      hipMemcpyDeviceToHost, c->stream));
+    if (!rc)
+        rc = check_hip(hipMemcpyAsync(&v[1], c->part_off + ntask, sizeof(uint32_t),
+                                      hipMemcpyDeviceToHost, c->stream));
+    if (!rc) rc = check_hip(hipStreamSynchronize(c->stream));
+    if (rc) return rc;
+    *pairs = v[0];
+    *staged = v[1];
+    return SDPD_OK;
+}
+
 int sdpd_get_tuning(sdpd_ctx *c, sdpd_tuning *out)
 {
     if (!c || !out) return SDPD_EINVAL;

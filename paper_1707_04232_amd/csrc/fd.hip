@@ -517,6 +517,7 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, uint64_t step, double dt_fd)
     if (c->prm.fd == SDPD_FD_NONE || c->n == 0) return SDPD_OK;
     int rc = run_schedule(c);
     if (rc) return rc;
+    c->fd_swept = 1;
     const int zero = 0;
     if ((rc = launch_phases(c, s, &zero, 1, step, dt_fd))) return rc;
     // levels of the inter-cell phases (phase 0 touches every cell and runs first)

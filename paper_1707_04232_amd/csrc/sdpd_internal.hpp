@@ -86,6 +86,7 @@ struct sdpd_ctx {
     double *obs_out;             // device stats records
     int64_t obs_cap;
     int cells_valid, masks_valid;
+    int fd_swept;                // a schedule has been built (sdpd_fd_schedule_size)
     sdpd_tuning tuning;          // F/D workgroup sizes and LDS capacities per phase class
     int max_lds;                 // LDS bytes one workgroup may use
     // pair schedule (rebuilt before every sweep)

@@ -21,7 +21,8 @@ TIMING_CLASSES = ("cells", "density", "fd", "forces", "observe", "schedule")
 EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
            "sdpd_copy_cell_start", "sdpd_density",
            "sdpd_forces", "sdpd_fd_metropolis", "sdpd_step", "sdpd_observe", "sdpd_sync",
-           "sdpd_set_timing", "sdpd_timing", "sdpd_tune", "sdpd_get_tuning", "sdpd_strerror",
+           "sdpd_set_timing", "sdpd_timing", "sdpd_tune", "sdpd_get_tuning",
+           "sdpd_fd_schedule_size", "sdpd_strerror",
            "sdpd_abi_version")
 
 
@@ -87,6 +88,7 @@ def lib():
             "sdpd_timing": [vp, C.POINTER(C.c_double), C.POINTER(i64)],
             "sdpd_tune": [vp, C.POINTER(_Tuning)],
             "sdpd_get_tuning": [vp, C.POINTER(_Tuning)],
+            "sdpd_fd_schedule_size": [vp, C.POINTER(i64), C.POINTER(i64)],
             "sdpd_abi_version": [],
         }
         for name, args in sig.items():
@@ -268,6 +270,13 @@ class Context:
             for k, v in enumerate(vals or (0, 0, 0, 0)):
                 arr[k] = int(v)
         _check(lib().sdpd_tune(self._h, C.byref(t)), "sdpd_tune")
+
+    def fd_schedule_size(self):
+        """(active pairs, staged particle entries) of the last F/D sweep."""
+        a, b = C.c_int64(), C.c_int64()
+        _check(lib().sdpd_fd_schedule_size(self._h, C.byref(a), C.byref(b)),
+               "sdpd_fd_schedule_size")
+        return a.value, b.value
 
     def get_tuning(self) -> dict:
         t = _Tuning()
