@@ -95,6 +95,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="workload name (the default is the headline 1M-particle case)")
+    ap.add_argument("--prec", choices=("fp64", "mixed"), default="fp64",
+                    help="arithmetic of the density and force passes")
+    ap.add_argument("--fd-every", type=int, default=1,
+                    help="F/D sweep every this many steps, with theta * dt (multiple time steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket kernels with HIP events")
@@ -112,7 +118,7 @@ def main():
     from paper_1707_04232_amd import sdpd
     from paper_1707_04232_amd.workload import WORKLOADS, workload_state
 
-    w = WORKLOADS[WORKLOAD]
+    w = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     if args.copy_calibration_mib:
         nbytes = args.copy_calibration_mib << 20
@@ -125,12 +131,14 @@ def main():
         del src, dst
     q, p, eps, ids = workload_state(w)
     S = sdpd.DeviceState.from_numpy(q, p, eps, ids)
+    prec = sdpd.MIXED if args.prec == "mixed" else sdpd.FP64
     prm = sdpd.SdpdParams(n=w.n, box=w.box, m=w.m, h=w.h, kB=w.kB, Cv=w.Cv, eta=w.eta,
-                          zeta=w.zeta, dt=w.dt, fd=sdpd.FD_EMS, seed=w.seed)
+                          zeta=w.zeta, dt=w.dt, fd=sdpd.FD_EMS, seed=w.seed, prec=prec,
+                          fd_every=args.fd_every)
     ctx = sdpd.Context(prm)
     ctx.prepare(S)
-    print(f"# {WORKLOAD}: n={w.n}, warmup {args.warmup}, timed {args.steps}", file=sys.stderr,
-          flush=True)
+    print(f"# {w.name}: n={w.n}, {args.prec}, warmup {args.warmup}, timed {args.steps}",
+          file=sys.stderr, flush=True)
     if args.warmup:
         ctx.step(S, 0, args.warmup, stats=False)
     ctx.sync()
@@ -162,7 +170,9 @@ def main():
         avg_ms = fd_ms / fd_launches
         flops_per_launch = FLOPS_PER_EMS_PAIR * proposed / fd_launches
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-        launches_per_sweep = fd_launches / args.steps
+        nsweeps = sum(1 for k in range(args.warmup, args.warmup + args.steps)
+                      if k % args.fd_every == 0)
+        launches_per_sweep = fd_launches / max(nsweeps, 1)
         alg_bytes = (last_staged * BYTES_PER_STAGED + last_pairs * BYTES_PER_PAIR_ENTRY) \
             / launches_per_sweep
         roof = {"bound": "alu", "kernel": "k_fd_phase", "achieved": achieved,
@@ -176,19 +186,23 @@ def main():
                  for k, v in tm.items()}
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == WORKLOAD:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w)
 
     out = {
-        "metric": "particle-steps/s (full SDPD step) at 1M particles; energy drift per 1e3 steps",
+        "metric": ("particle-steps/s (full SDPD step) at 1M particles; energy drift per 1e3 steps"
+                   if args.workload == WORKLOAD else
+                   f"particle-steps/s (full SDPD step) at {w.n} particles; energy drift per 1e3 steps"),
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": w.n, "lattice": list(w.dims), "box": list(w.box),
+        "config": {"workload": w.name, "n": w.n, "lattice": list(w.dims), "box": list(w.box),
                    "Cv": w.Cv, "T": w.T, "dt": w.dt, "h": w.h, "kernel": "lucy",
-                   "fd": "EMS", "steps": args.steps},
+                   "fd": "EMS", "fd_every": args.fd_every, "prec": args.prec,
+                   "steps": args.steps},
         "energy_drift": drift,
         "fd": {"pairs_per_step": proposed / args.steps,
                "staged_per_step_last": last_staged,

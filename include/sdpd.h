@@ -52,7 +52,13 @@ typedef enum { SDPD_KERNEL_LUCY = 0, SDPD_KERNEL_CUBIC = 1 } sdpd_kernel;
  * the Shardlow-like splitting without rejection (SSA, Sec. 3.2), or none.  */
 typedef enum { SDPD_FD_EMS = 0, SDPD_FD_AMS = 1, SDPD_FD_SSA = 2, SDPD_FD_NONE = 3 } sdpd_fd;
 
-typedef enum { SDPD_FP64 = 0 } sdpd_prec;
+/* arithmetic of the particle passes: everything in FP64, or (MIXED) the
+ * density, the pair masks and the pressure forces from FP32 positions
+ * relative to the particle's cell, FP32 kernel values and FP32 sums, while
+ * momenta, energies, the equation of state, the whole F/D update (with its
+ * Metropolis ratio) and the observables stay FP64.  MIXED decides r < h in
+ * FP32, so pairs within ~1e-7 h of the cutoff may differ from FP64.       */
+typedef enum { SDPD_FP64 = 0, SDPD_MIXED = 1 } sdpd_prec;
 
 /* Physical and numerical parameters.  Ideal-gas entropy closure
  *   S(eps, rho) = Cv ln eps - A kB ln(rho / rho0)          (eq. pg-eos)

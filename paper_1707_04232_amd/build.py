@@ -17,7 +17,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsdpd.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "cells.hip", "density.hip", "forces.hip", "schedule.hip", "fd.hip"]
+SOURCES = ["api.hip", "cells.hip", "density.hip", "forces.hip", "schedule.hip", "fd.hip",
+           "mixed.hip"]
 
 
 def hipcc() -> str:

@@ -61,7 +61,7 @@ static int check_params(const sdpd_params *P, int nc[3])
         return SDPD_EINVAL;                                   // kappa_perp > 0
     if (P->kernel != SDPD_KERNEL_LUCY && P->kernel != SDPD_KERNEL_CUBIC) return SDPD_EINVAL;
     if (P->fd < SDPD_FD_EMS || P->fd > SDPD_FD_NONE) return SDPD_EINVAL;
-    if (P->prec != SDPD_FP64) return SDPD_EINVAL;
+    if (P->prec != SDPD_FP64 && P->prec != SDPD_MIXED) return SDPD_EINVAL;
     if (P->cell_cap < 1 || P->cell_cap > MAX_CAP) return SDPD_EINVAL;
     if (P->fd_every < 1) return SDPD_EINVAL;
     int64_t ncell = 1;
@@ -122,6 +122,14 @@ static void derive(const sdpd_params *P, const int nc[3], DevParams &d)
     d.m_over_8 = P->m / 8.0;
     d.m_over_2 = P->m / 2.0;
     d.par_twice_perp = d.kpar_c == 2.0 * d.kperp_c;
+    d.mixed = P->prec == SDPD_MIXED;
+    for (int k = 0; k < 3; ++k) d.cell_f[k] = (float)(P->box[k] / nc[k]);
+    d.h_f = (float)h;
+    d.h2_f = (float)(h * h);
+    d.inv_h_f = (float)(1.0 / h);
+    d.m_f = (float)P->m;
+    d.cW_f = (float)d.cW;
+    d.cF_f = (float)d.cF;
 }
 
 template <typename T>
@@ -138,7 +146,7 @@ static void free_ctx(sdpd_ctx *c)
                     c->perm, c->cell_sorted, c->tq, c->tp, c->teps, c->trho, c->tf, c->tid,
                     c->pi, c->masks, c->counters, c->err, c->obs_partial, c->obs_out,
                     c->dparams, c->task_count, c->task_np, c->pair_off, c->part_off,
-                    c->part_list, c->pairs, c->draws};
+                    c->part_list, c->pairs, c->draws, c->qr, c->pi_f};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
@@ -270,6 +278,10 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     rc = rc ? rc : dalloc(&c->trho, n);
     rc = rc ? rc : dalloc(&c->tid, n);
     rc = rc ? rc : dalloc(&c->pi, n);
+    if (c->dp.mixed) {
+        rc = rc ? rc : dalloc(&c->qr, 3 * n);
+        rc = rc ? rc : dalloc(&c->pi_f, n);
+    }
     rc = rc ? rc : dalloc(&c->masks, (size_t)NNB * n);
     rc = rc ? rc : dalloc(&c->counters, (size_t)CNT_N);
     rc = rc ? rc : dalloc(&c->err, 1);

@@ -177,15 +177,25 @@ __global__ void k_rank(const uint32_t *tmp_idx, const uint32_t *cell_of,
     perm[s + rank] = i;
 }
 
-__global__ void k_gather(int64_t n, const uint32_t *perm, const uint32_t *cell_of,
+// gather into (cell, id) order; with qr (mixed precision) also the FP32
+// position relative to the particle's cell origin
+__global__ void k_gather(DevParams P, int64_t n, const uint32_t *perm, const uint32_t *cell_of,
                          const double *q, const double *p, const double *eps, const double *rho,
                          const double *f, const uint32_t *id, double *tq, double *tp,
                          double *teps, double *trho, double *tf, uint32_t *tid,
-                         uint32_t *cell_sorted)
+                         uint32_t *cell_sorted, float *qr)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     uint32_t i = perm[k];
+    if (qr) {
+        const uint32_t c = cell_of[i];
+        const int cc[3] = {(int)(c % (uint32_t)P.nc[0]), (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]),
+                           (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]))};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            qr[d * n + k] = (float)(q[d * n + i] - (double)cc[d] * (P.box[d] / P.nc[d]));
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         tq[c * n + k] = q[c * n + i];
@@ -235,9 +245,9 @@ int run_build_cells(sdpd_ctx *c, const sdpd_state *s, int kick_drift)
                            c->cursor, c->tmp_idx, n);
         hipLaunchKernelGGL(k_rank, dim3(g), dim3(256), 0, c->stream, c->tmp_idx, c->cell_of,
                            c->cell_start, s->id, c->perm, n, c->prm.cell_cap);
-        hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, n, c->perm, c->cell_of,
-                           s->q, s->p, s->eps, s->rho, s->f, s->id, c->tq, c->tp, c->teps,
-                           c->trho, c->tf, c->tid, c->cell_sorted);
+        hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, c->dp, n, c->perm,
+                           c->cell_of, s->q, s->p, s->eps, s->rho, s->f, s->id, c->tq, c->tp,
+                           c->teps, c->trho, c->tf, c->tid, c->cell_sorted, c->qr);
         if ((rc = check_hip(hipGetLastError()))) return rc;
         const size_t d3 = sizeof(double) * 3 * (size_t)n, d1 = sizeof(double) * (size_t)n;
         if ((rc = check_hip(hipMemcpyAsync(s->q, c->tq, d3, hipMemcpyDeviceToDevice, c->stream))))

@@ -76,6 +76,11 @@ int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps)
         c->masks_valid = 1;
         return SDPD_OK;
     }
+    if (c->dp.mixed) {
+        const int rc = run_density_f32(c, s, update_eps);
+        if (!rc) c->masks_valid = 1;
+        return rc;
+    }
     timer_begin(c, TK_DENSITY);
     hipLaunchKernelGGL(k_density, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, c->stream,
                        c->dp, s->q, c->cell_sorted, c->cell_start, s->rho, s->eps, update_eps,

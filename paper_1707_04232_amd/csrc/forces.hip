@@ -77,6 +77,7 @@ __global__ __launch_bounds__(256) void k_forces(DevParams P, const double *__res
 int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick)
 {
     if (c->n == 0) return SDPD_OK;
+    if (c->dp.mixed) return run_forces_f32(c, s, half_kick);
     const unsigned g = (unsigned)((c->n + 255) / 256);
     timer_begin(c, TK_FORCE);
     hipLaunchKernelGGL(k_pressure_term, dim3(g), dim3(256), 0, c->stream, c->dp, s->eps, s->rho,

@@ -1,0 +1,179 @@
+// Mixed-precision particle passes: SPH density (eq. sdpd-rho-v) with the
+// active-pair masks, and the conservative pressure forces (eq. cons-forces),
+// from FP32 positions relative to each particle's cell.  The separation of
+// particle i (cell c) and particle j found in the neighbour cell c + dk
+// (before the periodic wrap) is (xr_i - xr_j) - dk * cell_edge: no periodic
+// case analysis and no loss of digits to the box size.  Kernel values and the
+// per-particle sums are FP32; rho, f, eps and everything downstream (the
+// equation of state, the F/D update, the observables) stay FP64.
+#include "sdpd_internal.hpp"
+
+namespace sdpd {
+
+__device__ __forceinline__ float kernel_w_f32(const DevParams &P, float r)
+{
+    const float x = r * P.inv_h_f, t = 1.0f - x;
+    if (P.kernel == SDPD_KERNEL_LUCY) return P.cW_f * (1.0f + 3.0f * x) * (t * t * t);
+    if (x <= 0.5f) return P.cW_f * (1.0f - 6.0f * x * x + 6.0f * x * x * x);
+    return 2.0f * P.cW_f * (t * t * t);
+}
+
+__device__ __forceinline__ float kernel_f_f32(const DevParams &P, float r)
+{
+    const float x = r * P.inv_h_f, t = 1.0f - x;
+    if (P.kernel == SDPD_KERNEL_LUCY) return P.cF_f * (t * t);
+    if (x <= 0.5f) return P.cF_f * (2.0f - 3.0f * x);
+    return P.cF_f * P.h_f * (t * t) / r;
+}
+
+struct NbCellF {
+    int64_t c;
+    float sx, sy, sz;   // -dk * cell edge
+};
+
+__device__ __forceinline__ NbCellF neighbour_cell_f32(const DevParams &P, int cx, int cy, int cz,
+                                                      int k)
+{
+    const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+    NbCellF r;
+    r.sx = -(float)dx * P.cell_f[0];
+    r.sy = -(float)dy * P.cell_f[1];
+    r.sz = -(float)dz * P.cell_f[2];
+    int x2 = cx + dx, y2 = cy + dy, z2 = cz + dz;
+    x2 += x2 < 0 ? P.nc[0] : (x2 >= P.nc[0] ? -P.nc[0] : 0);
+    y2 += y2 < 0 ? P.nc[1] : (y2 >= P.nc[1] ? -P.nc[1] : 0);
+    z2 += z2 < 0 ? P.nc[2] : (z2 >= P.nc[2] ? -P.nc[2] : 0);
+    r.c = x2 + (int64_t)P.nc[0] * (y2 + (int64_t)P.nc[1] * z2);
+    return r;
+}
+
+// One thread per particle; candidates of the 27 cells in the fixed order;
+// masks[k * n + i] as in the FP64 pass (bit = slot of an active partner).
+__global__ __launch_bounds__(256) void k_density_f32(DevParams P, const float *__restrict__ qr,
+                                                     const uint32_t *__restrict__ cell_sorted,
+                                                     const uint32_t *__restrict__ cell_start,
+                                                     double *rho, double *eps, int update_eps,
+                                                     uint64_t *__restrict__ masks,
+                                                     uint32_t *err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const int64_t n = P.n;
+    const uint32_t c = cell_sorted[i];
+    const int cx = (int)(c % (uint32_t)P.nc[0]);
+    const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
+    const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
+    const float xi = qr[i], yi = qr[n + i], zi = qr[2 * n + i];
+    float acc = 0.0f;
+    for (int k = 0; k < 27; ++k) {
+        const NbCellF nb = neighbour_cell_f32(P, cx, cy, cz, k);
+        const uint32_t s = cell_start[nb.c], e = cell_start[nb.c + 1];
+        uint64_t mask = 0;
+        if (e - s > (uint32_t)P.cap) {   // overflowing cell: reported, not visited
+            atomicOr(err, ERR_CELLCAP);
+            masks[(int64_t)k * n + i] = 0ull;
+            continue;
+        }
+        for (uint32_t j = s; j < e; ++j) {
+            const float dx = (xi - qr[j]) + nb.sx;
+            const float dy = (yi - qr[n + j]) + nb.sy;
+            const float dz = (zi - qr[2 * n + j]) + nb.sz;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < P.h2_f) {
+                acc += P.m_f * kernel_w_f32(P, sqrtf(r2));
+                if (j != (uint32_t)i) mask |= 1ull << (j - s);
+            }
+        }
+        masks[(int64_t)k * n + i] = mask;
+    }
+    const double rho_new = (double)acc;
+    const double rho_old = rho[i];
+    rho[i] = rho_new;
+    if (update_eps) {
+        double e_new = eps[i] * pow(rho_new / rho_old, P.eps_exp);
+        if (!(e_new > 0.0) || !isfinite(e_new)) atomicOr(err, ERR_NONFINITE);
+        eps[i] = e_new;
+    }
+}
+
+__global__ void k_pressure_term_f32(DevParams P, const double *eps, const double *rho,
+                                    float *pi_f)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n) pi_f[i] = (float)(P.cPi * eps[i] / rho[i]);
+}
+
+// f_i over the partners recorded by the density pass, FP32 terms and sums
+__global__ __launch_bounds__(256) void k_forces_f32(DevParams P, const float *__restrict__ qr,
+                                                    const float *__restrict__ pi_f,
+                                                    const uint32_t *__restrict__ cell_sorted,
+                                                    const uint32_t *__restrict__ cell_start,
+                                                    const uint64_t *__restrict__ masks,
+                                                    double *f, double *p, int half_kick)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const int64_t n = P.n;
+    const uint32_t c = cell_sorted[i];
+    const int cx = (int)(c % (uint32_t)P.nc[0]);
+    const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
+    const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
+    const float xi = qr[i], yi = qr[n + i], zi = qr[2 * n + i];
+    const float pii = pi_f[i];
+    const float m2 = P.m_f * P.m_f;
+    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    for (int k = 0; k < 27; ++k) {
+        uint64_t mask = masks[(int64_t)k * n + i];
+        if (!mask) continue;
+        const NbCellF nb = neighbour_cell_f32(P, cx, cy, cz, k);
+        const uint32_t s = cell_start[nb.c];
+        while (mask) {
+            const uint32_t j = s + (uint32_t)__builtin_ctzll(mask);
+            mask &= mask - 1ull;
+            const float dx = (xi - qr[j]) + nb.sx;
+            const float dy = (yi - qr[n + j]) + nb.sy;
+            const float dz = (zi - qr[2 * n + j]) + nb.sz;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float sc = m2 * (pii + pi_f[j]) * kernel_f_f32(P, sqrtf(r2));
+            fx += sc * dx;
+            fy += sc * dy;
+            fz += sc * dz;
+        }
+    }
+    const double gx = fx, gy = fy, gz = fz;
+    f[i] = gx;
+    f[n + i] = gy;
+    f[2 * n + i] = gz;
+    if (half_kick) {
+        const double hd = 0.5 * P.dt;
+        p[i] += hd * gx;
+        p[n + i] += hd * gy;
+        p[2 * n + i] += hd * gz;
+    }
+}
+
+int run_density_f32(sdpd_ctx *c, const sdpd_state *s, int update_eps)
+{
+    timer_begin(c, TK_DENSITY);
+    hipLaunchKernelGGL(k_density_f32, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0,
+                       c->stream, c->dp, c->qr, c->cell_sorted, c->cell_start, s->rho, s->eps,
+                       update_eps, c->masks, c->err);
+    int rc = check_hip(hipGetLastError());
+    timer_end(c, TK_DENSITY);
+    return rc;
+}
+
+int run_forces_f32(sdpd_ctx *c, const sdpd_state *s, int half_kick)
+{
+    const unsigned g = (unsigned)((c->n + 255) / 256);
+    timer_begin(c, TK_FORCE);
+    hipLaunchKernelGGL(k_pressure_term_f32, dim3(g), dim3(256), 0, c->stream, c->dp, s->eps,
+                       s->rho, c->pi_f);
+    hipLaunchKernelGGL(k_forces_f32, dim3(g), dim3(256), 0, c->stream, c->dp, c->qr, c->pi_f,
+                       c->cell_sorted, c->cell_start, c->masks, s->f, s->p, half_kick);
+    int rc = check_hip(hipGetLastError());
+    timer_end(c, TK_FORCE);
+    return rc;
+}
+
+}  // namespace sdpd

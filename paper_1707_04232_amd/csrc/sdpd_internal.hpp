@@ -47,6 +47,10 @@ struct DevParams {
     double ent_c;       // Cv/kB - 1
     double m_over_8, m_over_2;
     int par_twice_perp;     // kpar_c == 2 kperp_c exactly (zeta = 0)
+    // mixed precision (prec == SDPD_MIXED): FP32 copies of the constants
+    int mixed;
+    float cell_f[3];        // cell edge lengths box / nc
+    float h_f, h2_f, inv_h_f, m_f, cW_f, cF_f;
 };
 
 // observable record (doubles): E, Eint, KE, P0, P1, P2, min_eps, then the
@@ -78,6 +82,7 @@ struct sdpd_ctx {
     double *tq, *tp, *teps, *trho, *tf;
     uint32_t *tid;
     double *pi;                  // P/rho^2 per particle
+    float *qr, *pi_f;            // mixed precision: positions relative to the cell, P/rho^2
     uint64_t *masks;             // NNB * n
     unsigned long long *counters;
     uint32_t *err;
@@ -113,6 +118,8 @@ int run_schedule(sdpd_ctx *c);
 int run_build_cells(sdpd_ctx *c, const sdpd_state *s, int kick_drift);
 int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps);
 int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick);
+int run_density_f32(sdpd_ctx *c, const sdpd_state *s, int update_eps);
+int run_forces_f32(sdpd_ctx *c, const sdpd_state *s, int half_kick);
 int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, uint64_t step, double dt_fd);
 void fd_default_tuning(sdpd_ctx *c);
 int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t);

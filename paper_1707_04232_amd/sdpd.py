@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_PKG, "libsdpd.so")
 OK, EINVAL, EHIP, ENOMEM, ECELLCAP, ENEGEPS, ENONFINITE, ECAPACITY = 0, -1, -2, -3, -4, -5, -6, -7
 KERNEL_LUCY, KERNEL_CUBIC = 0, 1
 FD_EMS, FD_AMS, FD_SSA, FD_NONE = 0, 1, 2, 3
+FP64, MIXED = 0, 1
 TIMING_CLASSES = ("cells", "density", "fd", "forces", "observe", "schedule")
 
 EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",

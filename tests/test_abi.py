@@ -78,7 +78,7 @@ BAD = [
     dict(fd_every=0),
     dict(dt=-1.0),
     dict(n=-1),
-    dict(prec=1),
+    dict(prec=2),
 ]
 
 
