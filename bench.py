@@ -90,6 +90,75 @@ def cpu_baseline(w, sample_dims=(64, 64, 64)):
             "cpu": platform.processor() or platform.machine()}
 
 
+def replicas_bench(args):
+    """Batched replicas: 256 boxes of uneven size and state, each a context of
+    its own, spread over 8 streams and advanced by one HIP graph; compared
+    with launching every box's step from the host in turn."""
+    import torch
+    from paper_1707_04232_amd import sdpd
+    from paper_1707_04232_amd.workload import lattice_state, replica_set
+    nbox = 256
+    boxes = replica_set(nbox, seed=0)
+    streams = [torch.cuda.Stream() for _ in range(8)]
+    ctxs, states, n_tot = [], [], 0
+    for b, (side, T, Cv) in enumerate(boxes):
+        q, p, eps, ids = lattice_state(side, Cv=Cv, T=T, seed=b)
+        prm = sdpd.SdpdParams(n=len(eps), box=float(side), Cv=Cv, replica=b)
+        S = sdpd.DeviceState.from_numpy(q, p, eps, ids)
+        with torch.cuda.stream(streams[b % len(streams)]):
+            ctx = sdpd.Context(prm)
+        ctx.prepare(S)
+        ctxs.append(ctx)
+        states.append(S)
+        n_tot += len(eps)
+    torch.cuda.synchronize()
+    print(f"# replicas: {nbox} boxes, {n_tot} particles, sides {min(b[0] for b in boxes)}.."
+          f"{max(b[0] for b in boxes)}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    B = sdpd.Batch(ctxs, states)
+    t_capture = time.perf_counter() - t0
+    B.run(0, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.run(args.warmup, args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for c in ctxs:
+        c.sync()
+    E = [c.observe(S)["E"] for c, S in zip(ctxs, states)]
+    # the same boxes stepped eagerly, box after box, from the host
+    k0 = args.warmup + args.steps
+    neager = max(2, min(20, args.steps // 10))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(neager):
+        for c, S in zip(ctxs, states):
+            c.step(S, k0 + k, 1, stats=False)
+    torch.cuda.synchronize()
+    el_eager = time.perf_counter() - t0
+    B.close()
+    for c in ctxs:
+        c.close()
+    value = n_tot * args.steps / el
+    out = {
+        "metric": "particle-steps/s (full SDPD step), 256 replica boxes in one HIP graph",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "replicas256", "boxes": nbox, "n_total": n_tot,
+                   "sides": [min(b[0] for b in boxes), max(b[0] for b in boxes)],
+                   "T_range": [0.1, 2.0], "Cv_range": [1.5, 50.0], "streams": len(streams),
+                   "dt": 0.005, "fd": "EMS"},
+        "eager_sequential": {"value": n_tot * neager / el_eager, "steps": neager,
+                             "ms_per_step": 1e3 * el_eager / neager},
+        "graph_speedup": (n_tot * args.steps / el) / (n_tot * neager / el_eager),
+        "capture_s": t_capture,
+        "sum_E_final": float(np.sum(E)),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +187,10 @@ def main():
     from paper_1707_04232_amd import sdpd
     from paper_1707_04232_amd.workload import WORKLOADS, workload_state
 
+    if args.workload == "replicas256":
+        torch.cuda.set_device(0)
+        replicas_bench(args)
+        return
     w = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     if args.copy_calibration_mib:

@@ -213,6 +213,26 @@ typedef struct {
 int sdpd_tune(sdpd_ctx *ctx, const sdpd_tuning *tuning);
 int sdpd_get_tuning(sdpd_ctx *ctx, sdpd_tuning *out);
 
+/* Batched replicas (many independent boxes advanced together).  Each box
+ * is a context of its own (its parameters, replica index, stream) with its
+ * state, prepared as for sdpd_step (cells, density, forces).  All contexts
+ * must share the device and fd_every, have timing off, appear once, and
+ * use created streams (not the null stream, which cannot be captured).
+ * sdpd_batch_create captures fd_every consecutive steps of every box into
+ * one HIP graph (it waits for the boxes' streams first; the graph refers to
+ * the given state arrays, which must stay allocated).  sdpd_batch_run
+ * replays it for steps step0 .. step0+nsteps-1 (both multiples of
+ * fd_every): every box advances exactly as with sdpd_step on its own (bit
+ * for bit), the boxes of different streams concurrently.  It is
+ * asynchronous: later work on a box's stream waits for it; sdpd_sync /
+ * sdpd_observe on a context report errors and observables.  Steps follow
+ * eq. (sdpd-verlet) with the F/D sweep of Sec. 3.3 as in sdpd_step.       */
+typedef struct sdpd_batch sdpd_batch;
+int sdpd_batch_create(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
+                      sdpd_batch **out);
+int sdpd_batch_run(sdpd_batch *batch, uint64_t step0, int nsteps);
+int sdpd_batch_destroy(sdpd_batch *batch);
+
 /* Size of the pair schedule of the last F/D sweep (sync): the number of
  * active pairs and the number of particle entries the phase workgroups
  * staged (a particle counts once per task it takes part in).  Zeros before

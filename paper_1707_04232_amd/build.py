@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libsdpd.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.hip", "cells.hip", "density.hip", "forces.hip", "schedule.hip", "fd.hip",
-           "mixed.hip"]
+           "mixed.hip", "batch.hip"]
 
 
 def hipcc() -> str:

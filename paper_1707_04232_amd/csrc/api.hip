@@ -146,7 +146,7 @@ static void free_ctx(sdpd_ctx *c)
                     c->perm, c->cell_sorted, c->tq, c->tp, c->teps, c->trho, c->tf, c->tid,
                     c->pi, c->masks, c->counters, c->err, c->obs_partial, c->obs_out,
                     c->dparams, c->task_count, c->task_np, c->pair_off, c->part_off,
-                    c->part_list, c->pairs, c->draws, c->qr, c->pi_f};
+                    c->part_list, c->pairs, c->draws, c->qr, c->pi_f, c->dstep};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
@@ -294,6 +294,7 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     rc = rc ? rc : dalloc(&c->part_off, (size_t)NMASK * nce + 1);
     rc = rc ? rc : dalloc(&c->pairs, (size_t)c->pair_cap);
     rc = rc ? rc : dalloc(&c->draws, (size_t)4 * c->pair_cap);
+    rc = rc ? rc : dalloc(&c->dstep, 1);
     rc = rc ? rc : dalloc(&c->part_list, (size_t)c->part_cap);
     if (!rc)
         rc = check_hip(hipMemcpyAsync(c->dparams, &c->dp, sizeof c->dp, hipMemcpyHostToDevice,
@@ -356,7 +357,8 @@ int sdpd_fd_metropolis(sdpd_ctx *c, const sdpd_state *s, uint64_t step, sdpd_sta
 {
     if (!c || !state_ok(c, s) || !c->cells_valid || !c->masks_valid) return SDPD_EINVAL;
     int rc = launch_fill_u64(c, c->counters, 0ull, CNT_N);
-    if (!rc) rc = run_fd_sweep(c, s, step, c->prm.dt * c->prm.fd_every);
+    if (!rc) rc = launch_fill_u64(c, (unsigned long long *)c->dstep, step, 1);
+    if (!rc) rc = run_fd_sweep(c, s, c->prm.dt * c->prm.fd_every);
     if (rc) return rc;
     if (out) {
         if ((rc = run_observe(c, s, c->obs_out))) return rc;
@@ -371,20 +373,42 @@ int sdpd_fd_metropolis(sdpd_ctx *c, const sdpd_state *s, uint64_t step, sdpd_sta
     return SDPD_OK;
 }
 
+}  // extern "C"
+
+namespace sdpd {
+
+// One full step (order B) enqueued on the context's stream, without any host
+// synchronisation.  With set_step the device step index is written first;
+// otherwise (a captured graph) it is taken as it is and advanced at the end.
+int enqueue_step(sdpd_ctx *c, const sdpd_state *s, uint64_t step, bool set_step)
+{
+    int rc;
+    const uint64_t theta = (uint64_t)c->prm.fd_every;
+    if ((rc = run_build_cells(c, s, 1))) return rc;
+    if ((rc = run_density(c, s, 1))) return rc;
+    if ((rc = launch_fill_u64(c, c->counters, 0ull, CNT_N))) return rc;
+    if (step % theta == 0) {
+        if (set_step &&
+            (rc = launch_fill_u64(c, (unsigned long long *)c->dstep, step, 1)))
+            return rc;
+        if ((rc = run_fd_sweep(c, s, c->prm.dt * (double)theta))) return rc;
+    }
+    if ((rc = run_forces(c, s, 1))) return rc;
+    if (!set_step && (rc = launch_incr_u64(c, (unsigned long long *)c->dstep))) return rc;
+    return SDPD_OK;
+}
+
+}  // namespace sdpd
+
+extern "C" {
+
 int sdpd_step(sdpd_ctx *c, const sdpd_state *s, uint64_t step0, int nsteps, sdpd_stats *per_step)
 {
     if (!c || !state_ok(c, s) || nsteps < 0 || !c->cells_valid) return SDPD_EINVAL;
     int rc;
     if (per_step && (rc = ensure_records(c, nsteps))) return rc;
-    const uint64_t theta = (uint64_t)c->prm.fd_every;
     for (int k = 0; k < nsteps; ++k) {
-        const uint64_t step = step0 + (uint64_t)k;
-        if ((rc = run_build_cells(c, s, 1))) return rc;
-        if ((rc = run_density(c, s, 1))) return rc;
-        if ((rc = launch_fill_u64(c, c->counters, 0ull, CNT_N))) return rc;
-        if (step % theta == 0 && (rc = run_fd_sweep(c, s, step, c->prm.dt * (double)theta)))
-            return rc;
-        if ((rc = run_forces(c, s, 1))) return rc;
+        if ((rc = enqueue_step(c, s, step0 + (uint64_t)k, true))) return rc;
         if (per_step) {
             timer_begin(c, TK_OBSERVE);
             rc = run_observe(c, s, c->obs_out + (size_t)k * REC);

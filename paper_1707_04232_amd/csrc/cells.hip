@@ -210,6 +210,17 @@ __global__ void k_gather(DevParams P, int64_t n, const uint32_t *perm, const uin
 
 static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+__global__ void k_incr_u64(unsigned long long *p)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p += 1ull;
+}
+
+int launch_incr_u64(sdpd_ctx *c, unsigned long long *p)
+{
+    hipLaunchKernelGGL(k_incr_u64, dim3(1), dim3(64), 0, c->stream, p);
+    return check_hip(hipGetLastError());
+}
+
 int launch_fill_u32(sdpd_ctx *c, uint32_t *p, uint32_t v, int64_t n)
 {
     if (n <= 0) return SDPD_OK;

@@ -105,7 +105,8 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                                                  const uint64_t *__restrict__ pairs,
                                                  const uint32_t *__restrict__ part_list,
                                                  uint32_t pair_cap, uint32_t part_cap,
-                                                 uint32_t step, double dt, double *draws,
+                                                 const uint64_t *__restrict__ dstep, double dt,
+                                                 double *draws,
                                                  unsigned long long *counters, uint32_t *err)
 {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -283,6 +284,7 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
             // draws of the window's pairs in sorted order, all lanes busy; the
             // ids also orient each entry (A side = smaller id)
             {
+                const uint32_t step = (uint32_t)*dstep;   // step index of the Philox counter
                 const int ntot = min(*s_ntot, CE);
                 double *wdraws = draws + 4 * (int64_t)e_begin;
                 constexpr int DPL = 4;   // entries per lane per pass: id loads in flight
@@ -477,7 +479,7 @@ int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t)
 
 // one launch over the tasks of up to FD_MAXPH mutually disjoint phases
 static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, int nph,
-                         uint64_t step, double dt_fd)
+                         double dt_fd)
 {
     FdLaunch L;
     L.nph = nph;
@@ -507,19 +509,21 @@ static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, in
     hipLaunchKernelGGL(k_fd_phase, dim3((unsigned)wg), dim3(64), lds, c->stream, c->dparams, L,
                        s->q, s->p, s->eps, s->rho, s->id, c->pair_off, c->part_off, c->pairs,
                        c->part_list, (uint32_t)c->pair_cap, (uint32_t)c->part_cap,
-                       (uint32_t)step, dt_fd, c->draws, c->counters, c->err);
+                       c->dstep, dt_fd, c->draws, c->counters, c->err);
     timer_end(c, TK_FD);
     return check_hip(hipGetLastError());
 }
 
-int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, uint64_t step, double dt_fd)
+// The step index of the draws is read from c->dstep on the device (set by
+// the caller, or advanced inside a captured graph).
+int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
 {
     if (c->prm.fd == SDPD_FD_NONE || c->n == 0) return SDPD_OK;
     int rc = run_schedule(c);
     if (rc) return rc;
     c->fd_swept = 1;
     const int zero = 0;
-    if ((rc = launch_phases(c, s, &zero, 1, step, dt_fd))) return rc;
+    if ((rc = launch_phases(c, s, &zero, 1, dt_fd))) return rc;
     // levels of the inter-cell phases (phase 0 touches every cell and runs first)
     int lvl[105];
     unsigned set[105];
@@ -537,11 +541,11 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, uint64_t step, double dt_fd)
             if (lvl[p] != l) continue;
             group[ng++] = p;
             if (ng == FD_MAXPH) {
-                if ((rc = launch_phases(c, s, group, ng, step, dt_fd))) return rc;
+                if ((rc = launch_phases(c, s, group, ng, dt_fd))) return rc;
                 ng = 0;
             }
         }
-        if (ng && (rc = launch_phases(c, s, group, ng, step, dt_fd))) return rc;
+        if (ng && (rc = launch_phases(c, s, group, ng, dt_fd))) return rc;
     }
     return SDPD_OK;
 }

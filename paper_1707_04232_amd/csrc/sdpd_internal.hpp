@@ -98,6 +98,7 @@ struct sdpd_ctx {
     uint32_t *task_count, *task_np, *pair_off, *part_off, *part_list;
     uint64_t *pairs;
     double *draws;               // 4 per pair entry: the sweep's random draws in sorted order
+    uint64_t *dstep;             // step index of the draws, on the device
     int64_t pair_cap, part_cap;
     sdpd::Timer timer;
     int timing;
@@ -112,6 +113,7 @@ int check_hip(hipError_t e);
 // host launchers (each returns an sdpd_status)
 int launch_fill_u32(sdpd_ctx *c, uint32_t *p, uint32_t v, int64_t n);
 int launch_fill_u64(sdpd_ctx *c, unsigned long long *p, unsigned long long v, int64_t n);
+int launch_incr_u64(sdpd_ctx *c, unsigned long long *p);
 int run_scan(sdpd_ctx *c, const uint32_t *in, uint32_t *out, int64_t count, uint32_t *block_sums,
              int cap);
 int run_schedule(sdpd_ctx *c);
@@ -120,7 +122,8 @@ int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps);
 int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick);
 int run_density_f32(sdpd_ctx *c, const sdpd_state *s, int update_eps);
 int run_forces_f32(sdpd_ctx *c, const sdpd_state *s, int half_kick);
-int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, uint64_t step, double dt_fd);
+int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd);
+int enqueue_step(sdpd_ctx *c, const sdpd_state *s, uint64_t step, bool set_step);
 void fd_default_tuning(sdpd_ctx *c);
 int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t);
 int run_observe(sdpd_ctx *c, const sdpd_state *s, double *dst_record);

@@ -23,7 +23,8 @@ EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
            "sdpd_copy_cell_start", "sdpd_density",
            "sdpd_forces", "sdpd_fd_metropolis", "sdpd_step", "sdpd_observe", "sdpd_sync",
            "sdpd_set_timing", "sdpd_timing", "sdpd_tune", "sdpd_get_tuning",
-           "sdpd_fd_schedule_size", "sdpd_strerror",
+           "sdpd_fd_schedule_size", "sdpd_batch_create", "sdpd_batch_run",
+           "sdpd_batch_destroy", "sdpd_strerror",
            "sdpd_abi_version")
 
 
@@ -90,6 +91,9 @@ def lib():
             "sdpd_tune": [vp, C.POINTER(_Tuning)],
             "sdpd_get_tuning": [vp, C.POINTER(_Tuning)],
             "sdpd_fd_schedule_size": [vp, C.POINTER(i64), C.POINTER(i64)],
+            "sdpd_batch_create": [C.POINTER(vp), C.POINTER(_State), i32, C.POINTER(vp)],
+            "sdpd_batch_run": [vp, u64, i32],
+            "sdpd_batch_destroy": [vp],
             "sdpd_abi_version": [],
         }
         for name, args in sig.items():
@@ -290,3 +294,31 @@ class Context:
         self.build_cells(s)
         self.density(s, update_eps=False)
         self.forces(s)
+
+
+class Batch:
+    """Many boxes (contexts with their states) advanced by one HIP graph."""
+
+    def __init__(self, contexts, states):
+        self._ctx = list(contexts)
+        self._st = list(states)
+        n = len(self._ctx)
+        handles = (C.c_void_p * n)(*[c._h.value for c in self._ctx])
+        self._cst = (_State * n)(*[s.c() for s in self._st])
+        self._h = C.c_void_p()
+        _check(lib().sdpd_batch_create(handles, self._cst, n, C.byref(self._h)),
+               "sdpd_batch_create")
+
+    def run(self, step0: int, nsteps: int):
+        _check(lib().sdpd_batch_run(self._h, int(step0), int(nsteps)), "sdpd_batch_run")
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().sdpd_batch_destroy(self._h)
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

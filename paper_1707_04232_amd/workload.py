@@ -97,3 +97,15 @@ def shuffled(q, p, eps, ids, seed: int = 1):
     perm = np.random.default_rng(seed).permutation(eps.shape[0])
     return (np.ascontiguousarray(q[:, perm]), np.ascontiguousarray(p[:, perm]),
             eps[perm].copy(), ids[perm].copy())
+
+
+def replica_set(nbox: int = 256, seed: int = 0):
+    """A batch of independent boxes of uneven size and state: n_b =
+    round(exp(U[ln 2048, ln 65536])^(1/3)) lattice sites per side (13..40),
+    T_b ~ U[0.1, 2], C_v,b ~ U[1.5, 50] (k_B = 1), replica index b.  Returns
+    a list of (side, T, Cv)."""
+    rng = np.random.default_rng(seed)
+    sides = np.rint(np.exp(rng.uniform(np.log(2048.0), np.log(65536.0), nbox)) ** (1.0 / 3.0))
+    T = rng.uniform(0.1, 2.0, nbox)
+    Cv = rng.uniform(1.5, 50.0, nbox)
+    return [(int(s), float(t), float(c)) for s, t, c in zip(sides, T, Cv)]
