@@ -159,6 +159,74 @@ def replicas_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def adjoint_bench(args):
+    """Adjoint of the conservative dynamics on a 64^3 lattice (C_v = 10,
+    T = 1, F/D off): K = 50 steps forward with checkpoints every 10, then the
+    reverse pass; the gradient is checked against central differences of the
+    forward along one random direction."""
+    import torch
+    from paper_1707_04232_amd import sdpd
+    from paper_1707_04232_amd.workload import WORKLOADS, workload_state
+    w = WORKLOADS["lattice64_cv10"]
+    K, every = 50, 10
+    q, p, eps, ids = workload_state(w)
+    prm = sdpd.SdpdParams(n=w.n, box=w.box, Cv=w.Cv, dt=w.dt, fd=sdpd.FD_NONE)
+    rng = np.random.default_rng(1)
+    a = torch.as_tensor(rng.normal(size=(3, w.n)), device="cuda")
+    b = torch.as_tensor(rng.normal(size=(3, w.n)), device="cuda")
+
+    def forward(qq):
+        S = sdpd.DeviceState.from_numpy(qq, p, eps, ids)
+        ctx = sdpd.Context(prm)
+        ctx.prepare(S)
+        return ctx, S
+
+    def J_of(S):
+        order = S.id.long()
+        return float((a[:, order] * S.q).sum() + (b[:, order] * S.p).sum())
+
+    ctx, S = forward(q)
+    for _ in range(2):   # warm up the code paths
+        c2, S2 = forward(q)
+        c2.adjoint_forward(S2, K, every)
+        c2.adjoint_backward(a, b)
+        c2.sync()
+        c2.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.adjoint_forward(S, K, every)
+    ctx.sync()
+    t1 = time.perf_counter()
+    dq, dp, de, dA = ctx.adjoint_backward(a, b)
+    ctx.sync()
+    t2 = time.perf_counter()
+    ctx.close()
+    d = rng.normal(size=q.shape)
+    delta = 1e-6
+    Js = []
+    for sgn in (1, -1):
+        c, Sx = forward(q + sgn * delta * d)
+        c.step(Sx, 0, K, stats=False)
+        c.sync()
+        Js.append(J_of(Sx))
+        c.close()
+    fd = (Js[0] - Js[1]) / (2 * delta)
+    ad = float((dq.cpu().numpy()[:, ids] * d).sum())
+    out = {
+        "metric": "particle-steps/s of the adjoint (forward with checkpoints + reverse), 64^3",
+        "value": w.n * K / (t2 - t0), "unit": "particle-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": 2, "ms_per_step": 1e3 * (t2 - t0) / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "adjoint64", "n": w.n, "lattice": list(w.dims), "Cv": w.Cv,
+                   "T": w.T, "dt": w.dt, "steps": K, "checkpoint_every": every, "fd": "none"},
+        "forward_s": t1 - t0, "backward_s": t2 - t1,
+        "directional_derivative": {"adjoint": ad, "central_differences": fd, "delta": delta,
+                                   "rel_diff": abs(ad - fd) / abs(fd)},
+        "dJ_dA": dA,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +258,10 @@ def main():
     if args.workload == "replicas256":
         torch.cuda.set_device(0)
         replicas_bench(args)
+        return
+    if args.workload == "adjoint64":
+        torch.cuda.set_device(0)
+        adjoint_bench(args)
         return
     w = WORKLOADS[args.workload]
     torch.cuda.set_device(0)

@@ -233,6 +233,26 @@ int sdpd_batch_create(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
 int sdpd_batch_run(sdpd_batch *batch, uint64_t step0, int nsteps);
 int sdpd_batch_destroy(sdpd_batch *batch);
 
+/* Adjoint of the conservative dynamics (F/D off: params.fd = SDPD_FD_NONE,
+ * FP64): reverse-mode gradients of a scalar J(q_K, p_K) with respect to the
+ * initial positions, momenta and internal energies and to the closure
+ * coefficient A, through K steps of eq. (sdpd-verlet) with the density of
+ * eq. (sdpd-rho-v), the entropy-conserving energies of Sec. 3.1 (the
+ * entropies follow from eps0 and rho(q0), so rho0 cancels) and the forces of
+ * eq. (cons-forces).  sdpd_adjoint_forward advances the prepared state by
+ * nsteps steps (as sdpd_step does), keeping a copy of the full state every
+ * checkpoint_every steps in the context; particle ids must be 0..n-1
+ * (SDPD_EINVAL from the next synchronising call otherwise).
+ * sdpd_adjoint_backward takes dJ/dq_K and dJ/dp_K (device, 3 x n planes,
+ * indexed by particle id) and writes dJ/dq0, dJ/dp0 (device, same layout),
+ * dJ/deps0 (device, n by id; may be NULL) and dJ/dA (host scalar; may be
+ * NULL; its computation synchronises).  It recomputes each segment from its
+ * checkpoint; memory: (nsteps / checkpoint_every + checkpoint_every + 2)
+ * full states.                                                             */
+int sdpd_adjoint_forward(sdpd_ctx *ctx, sdpd_state *state, int nsteps, int checkpoint_every);
+int sdpd_adjoint_backward(sdpd_ctx *ctx, const double *dJ_dq, const double *dJ_dp,
+                          double *dJ_dq0, double *dJ_dp0, double *dJ_deps0, double *dJ_dA);
+
 /* Size of the pair schedule of the last F/D sweep (sync): the number of
  * active pairs and the number of particle entries the phase workgroups
  * staged (a particle counts once per task it takes part in).  Zeros before

@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libsdpd.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.hip", "cells.hip", "density.hip", "forces.hip", "schedule.hip", "fd.hip",
-           "mixed.hip", "batch.hip"]
+           "mixed.hip", "batch.hip", "adjoint.hip"]
 
 
 def hipcc() -> str:

@@ -150,6 +150,7 @@ static void free_ctx(sdpd_ctx *c)
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
+    adjoint_free(c->adj);
     delete c;
 }
 
@@ -170,6 +171,7 @@ static int take_error(sdpd_ctx *c)
         uint32_t z = 0;
         if (hipMemcpy(c->err, &z, sizeof z, hipMemcpyHostToDevice) != hipSuccess) return SDPD_EHIP;
     }
+    if (e & ERR_IDS) return SDPD_EINVAL;
     if (e & ERR_CELLCAP) return SDPD_ECELLCAP;
     if (e & ERR_NONFINITE) return SDPD_ENONFINITE;
     if (e & ERR_PAIRCAP) return SDPD_ECAPACITY;

@@ -11,7 +11,10 @@
 namespace sdpd {
 
 // sticky device error bits
-enum : uint32_t { ERR_CELLCAP = 1u, ERR_NEGEPS = 2u, ERR_NONFINITE = 4u, ERR_PAIRCAP = 8u };
+enum : uint32_t {
+    ERR_CELLCAP = 1u, ERR_NEGEPS = 2u, ERR_NONFINITE = 4u, ERR_PAIRCAP = 8u, ERR_IDS = 16u
+};
+struct AdjointWork;   // adjoint.hip
 
 // F/D counters, in this order in the device counter array
 enum { CNT_PROPOSED = 0, CNT_REJ_ENERGY, CNT_REJ_RATIO, CNT_MARGINAL, CNT_NEGEPS, CNT_N };
@@ -99,6 +102,7 @@ struct sdpd_ctx {
     uint64_t *pairs;
     double *draws;               // 4 per pair entry: the sweep's random draws in sorted order
     uint64_t *dstep;             // step index of the draws, on the device
+    sdpd::AdjointWork *adj;      // checkpoints and cotangents of the adjoint (lazily)
     int64_t pair_cap, part_cap;
     sdpd::Timer timer;
     int timing;
@@ -127,6 +131,7 @@ int enqueue_step(sdpd_ctx *c, const sdpd_state *s, uint64_t step, bool set_step)
 void fd_default_tuning(sdpd_ctx *c);
 int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t);
 int run_observe(sdpd_ctx *c, const sdpd_state *s, double *dst_record);
+void adjoint_free(AdjointWork *a);
 
 // event timing around one launch of class k (no-op unless c->timing)
 void timer_begin(sdpd_ctx *c, int k);

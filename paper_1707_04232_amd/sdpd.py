@@ -24,7 +24,8 @@ EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
            "sdpd_forces", "sdpd_fd_metropolis", "sdpd_step", "sdpd_observe", "sdpd_sync",
            "sdpd_set_timing", "sdpd_timing", "sdpd_tune", "sdpd_get_tuning",
            "sdpd_fd_schedule_size", "sdpd_batch_create", "sdpd_batch_run",
-           "sdpd_batch_destroy", "sdpd_strerror",
+           "sdpd_batch_destroy", "sdpd_adjoint_forward", "sdpd_adjoint_backward",
+           "sdpd_strerror",
            "sdpd_abi_version")
 
 
@@ -94,6 +95,8 @@ def lib():
             "sdpd_batch_create": [C.POINTER(vp), C.POINTER(_State), i32, C.POINTER(vp)],
             "sdpd_batch_run": [vp, u64, i32],
             "sdpd_batch_destroy": [vp],
+            "sdpd_adjoint_forward": [vp, SP, i32, i32],
+            "sdpd_adjoint_backward": [vp, vp, vp, vp, vp, vp, C.POINTER(C.c_double)],
             "sdpd_abi_version": [],
         }
         for name, args in sig.items():
@@ -275,6 +278,25 @@ class Context:
             for k, v in enumerate(vals or (0, 0, 0, 0)):
                 arr[k] = int(v)
         _check(lib().sdpd_tune(self._h, C.byref(t)), "sdpd_tune")
+
+    def adjoint_forward(self, s: DeviceState, nsteps: int, checkpoint_every: int = 10):
+        _check(lib().sdpd_adjoint_forward(self._h, C.byref(s.c()), int(nsteps),
+                                          int(checkpoint_every)), "sdpd_adjoint_forward")
+
+    def adjoint_backward(self, dJ_dq, dJ_dp):
+        """dJ/dq_K, dJ/dp_K: float64 (3, n) device tensors indexed by particle
+        id.  Returns (dJ/dq0, dJ/dp0, dJ/deps0, dJ/dA), id-indexed tensors."""
+        import torch
+        n = dJ_dq.shape[1]
+        dq0 = torch.empty((3, n), dtype=torch.float64, device=dJ_dq.device)
+        dp0 = torch.empty_like(dq0)
+        de0 = torch.empty((n,), dtype=torch.float64, device=dJ_dq.device)
+        dA = C.c_double()
+        a, b = dJ_dq.contiguous(), dJ_dp.contiguous()
+        _check(lib().sdpd_adjoint_backward(self._h, a.data_ptr(), b.data_ptr(), dq0.data_ptr(),
+                                           dp0.data_ptr(), de0.data_ptr(), C.byref(dA)),
+               "sdpd_adjoint_backward")
+        return dq0, dp0, de0, dA.value
 
     def fd_schedule_size(self):
         """(active pairs, staged particle entries) of the last F/D sweep."""
