@@ -96,6 +96,8 @@ __device__ __forceinline__ void fd_gather(const uint32_t *s_sorted, const uint32
     g.lnU = d23.y;
 }
 
+// FAST: the common case (EMS, Lucy kernel, zeta = 0) fixed at compile time
+template <bool FAST>
 __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ Pp, FdLaunch L,
                                                  const double *__restrict__ q, double *p,
                                                  double *eps, const double *__restrict__ rho,
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                     nval = e < (int)(s_off[nl] + s_hist[nl]);
                     if (nval) fd_gather(s_sorted, s_gidx, q, rho, wdr, n, e, nli, nlj, nxt);
                 }
-                if (cval) fd_pair(P, dt, cli, clj, cur, s_p, CP, s_eps, cnt, negeps);
+                if (cval) fd_pair<FAST>(P, dt, cli, clj, cur, s_p, CP, s_eps, cnt, negeps);
                 __syncthreads();
                 cur = nxt;
                 cli = nli;
@@ -456,7 +458,10 @@ void fd_default_tuning(sdpd_ctx *c)
     }
     if (c->max_lds > 65536) {
         // allow dynamic LDS beyond 64 KiB where the device has it
-        if (hipFuncSetAttribute((const void *)k_fd_phase,
+        if (hipFuncSetAttribute((const void *)k_fd_phase<false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                c->max_lds) != hipSuccess ||
+            hipFuncSetAttribute((const void *)k_fd_phase<true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 c->max_lds) != hipSuccess) {
             (void)hipGetLastError();
@@ -506,7 +511,10 @@ static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, in
     const size_t lds = fd_lds_bytes(L.cap_p, L.cap_e);
     if (lds > (size_t)c->max_lds) return SDPD_EINVAL;
     timer_begin(c, TK_FD);
-    hipLaunchKernelGGL(k_fd_phase, dim3((unsigned)wg), dim3(64), lds, c->stream, c->dparams, L,
+    const bool fast = c->dp.fd == SDPD_FD_EMS && c->dp.kernel == SDPD_KERNEL_LUCY &&
+                      c->dp.par_twice_perp;
+    auto kern = fast ? k_fd_phase<true> : k_fd_phase<false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)wg), dim3(64), lds, c->stream, c->dparams, L,
                        s->q, s->p, s->eps, s->rho, s->id, c->pair_off, c->part_off, c->pairs,
                        c->part_list, (uint32_t)c->pair_cap, (uint32_t)c->part_cap,
                        c->dstep, dt_fd, c->draws, c->counters, c->err);

@@ -69,6 +69,8 @@ struct Coef {
 
 // When zeta = 0 the parallel friction is exactly twice the perpendicular one,
 // and expm1(2y) = e (2 + e) with e = expm1(y) saves one exponential.
+// FAST = the common case fixed at compile time: EMS, Lucy kernel, zeta = 0
+template <bool FAST>
 __device__ __forceinline__ Coef fd_coef(const DevParams &P, double kpar, double kperp, double ei,
                                         double ej, double dt)
 {
@@ -80,7 +82,7 @@ __device__ __forceinline__ Coef fd_coef(const DevParams &P, double kpar, double 
     const double omd = 1.0 - d;
     const double c = -2.0 * dt * P.inv_m * omd;
     const double e_perp = expm1(c * kperp);
-    const double e_par = P.par_twice_perp ? e_perp * (2.0 + e_perp) : expm1(c * kpar);
+    const double e_par = (FAST || P.par_twice_perp) ? e_perp * (2.0 + e_perp) : expm1(c * kpar);
     const double s = P.b2_c * Tred * fast_rcp(omd);
     Coef r;
     r.al_par = 1.0 + e_par;
@@ -116,6 +118,7 @@ __device__ __forceinline__ void pair_draws_log(const DevParams &P, uint32_t step
 
 // One pair update; li has the smaller id.  Momenta (x, y, z planes at
 // stride ps) and energies are LDS-resident.
+template <bool FAST>
 __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
                                         int lj, const PairGeo &pg, double *s_p, int ps,
                                         double *s_eps, FdCount &cnt, bool &negeps)
@@ -131,7 +134,7 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
     const double ex = dx * inv_r, ey = dy * inv_r, ez = dz * inv_r;
     const double x = r * P.inv_h, t = 1.0 - x;
     double F;
-    if (P.kernel == SDPD_KERNEL_LUCY) F = P.cF * (t * t);
+    if (FAST || P.kernel == SDPD_KERNEL_LUCY) F = P.cF * (t * t);
     else F = x <= 0.5 ? P.cF * (2.0 - 3.0 * x) : P.cF * P.h * (t * t) * inv_r;
     // kappa^theta of Sec. 2.2.2
     const double kfac = F * fast_rcp(pg.rho_i * pg.rho_j);
@@ -145,7 +148,7 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
     const double G[3] = {pg.G0, pg.G1, pg.G2};
 
     // proposal, eq. (proposal): v' = A(v) v + B(v) G, B = (2/m) zeta^theta P^theta
-    const Coef f = fd_coef(P, kpar, kperp, ei, ej, dt);
+    const Coef f = fd_coef<FAST>(P, kpar, kperp, ei, ej, dt);
     const double b_par = fd_sqrt(f.b2_par), b_perp = fd_sqrt(f.b2_perp);
     const double vpar = vx * ex + vy * ey + vz * ez;
     const double Gpar = G[0] * ex + G[1] * ey + G[2] * ez;
@@ -162,7 +165,7 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
     const double emin = fmin(ei, ej);
     bool accept = true;
     cnt.proposed += 1;
-    if (P.fd == SDPD_FD_SSA) {
+    if (!FAST && P.fd == SDPD_FD_SSA) {
         if (!(ei - delta > 0.0 && ej - delta > 0.0)) {
             cnt.negeps += 1;
             negeps = true;
@@ -172,10 +175,10 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
         if (!(emin > delta)) {                       // eq. (energy-bound)
             accept = false;
             cnt.rej_energy += 1;
-        } else if (P.fd == SDPD_FD_EMS) {
+        } else if (FAST || P.fd == SDPD_FD_EMS) {
             // reverse move from v' at the proposed energies, eq. (metropolis-ratio)
             const double ei2 = ei - delta, ej2 = ej - delta;
-            const Coef g = fd_coef(P, kpar, kperp, ei2, ej2, dt);
+            const Coef g = fd_coef<FAST>(P, kpar, kperp, ei2, ej2, dt);
             const double wpar = vpar - g.al_par * npar;
             const double wqx = vqx - g.al_perp * nqx;
             const double wqy = vqy - g.al_perp * nqy;
