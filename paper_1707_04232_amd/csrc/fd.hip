@@ -417,15 +417,18 @@ PhaseGeom phase_geom(int phase)
 
 // per-task staging allowance at 17.5 particles per cell: mean participants
 // and pair entries per task, and their spread (standard deviation per task),
-// measured on jittered lattices
+// measured on jittered lattices; then a headroom factor on both capacities.
+// The own-cell phase gains from room for the heavy ranges (lattice cells of
+// 27 particles) while it stays under 20 KB, the LDS share of one of the 8
+// workgroups a CU holds at two waves per SIMD.
 struct Allow {
-    double mp, sp, me, se;
+    double mp, sp, me, se, room;
 };
 constexpr Allow kAllow[4] = {
-    {17.5, 5.5, 143.0, 50.0},   // own cell
-    {26.2, 10.0, 102.0, 59.0},  // face
-    {14.7, 10.0, 25.2, 20.0},   // edge
-    {6.7, 5.0, 5.4, 4.5},       // corner
+    {17.5, 5.5, 143.0, 50.0, 1.25},   // own cell
+    {26.2, 10.0, 102.0, 59.0, 1.0},   // face
+    {14.7, 10.0, 25.2, 20.0, 1.0},    // edge
+    {6.7, 5.0, 5.4, 4.5, 1.0},        // corner
 };
 constexpr int kDefaultTasks[4] = {8, 8, 16, 48};
 
@@ -443,8 +446,9 @@ void fd_default_tuning(sdpd_ctx *c)
     for (int k = 0; k < 4; ++k) {
         const int t = kDefaultTasks[k];
         const double st = std::sqrt((double)t);
-        int cp = round_up((t * kAllow[k].mp + 4.0 * st * kAllow[k].sp) * s, 16);
-        int ce = round_up((t * kAllow[k].me + 4.0 * st * kAllow[k].se) * s * s, 64);
+        const double room = kAllow[k].room;
+        int cp = round_up((t * kAllow[k].mp + 4.0 * st * kAllow[k].sp) * s * room, 16);
+        int ce = round_up((t * kAllow[k].me + 4.0 * st * kAllow[k].se) * s * s * room, 64);
         cp = std::min(std::max(cp, 128), 65535);
         ce = std::max(ce, 64);
         // shrink to the LDS limit, keeping the particle / pair proportion
