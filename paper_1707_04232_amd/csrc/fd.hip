@@ -93,7 +93,7 @@ __device__ __forceinline__ void fd_gather(const uint32_t *s_sorted, const uint32
     g.G0 = d01.x;
     g.G1 = d01.y;
     g.G2 = d23.x;
-    g.lnU = d23.y;
+    g.U = d23.y;
 }
 
 // FAST: the common case (EMS, Lucy kernel, zeta = 0) fixed at compile time
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                                 i1 = t;
                             }
                             double d[4];
-                            pair_draws_log(P, step, i0, i1, d);
+                            pair_draws_stored(P, step, i0, i1, d);
                             double2 *dst = reinterpret_cast<double2 *>(wdraws) + 2 * (int64_t)e;
                             dst[0] = make_double2(d[0], d[1]);
                             dst[1] = make_double2(d[2], d[3]);
@@ -321,44 +321,55 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
             }
             __syncthreads();
             // level steps: (level, first sorted position) in ascending order;
-            // the read-only data of step k + 1 is gathered before step k runs
+            // the read-only data of steps k + 1 and k + 2 is in flight while
+            // step k runs (the gathers only read LDS entries fixed above)
             const int top = *s_maxlv;
             const double *wdr = draws + 4 * (int64_t)e_begin;
-            int l = lo, b0 = (int)s_off[lo];
-            while (l <= top && b0 >= (int)(s_off[l] + s_hist[l])) {
-                ++l;
-                if (l <= top) b0 = (int)s_off[l];
-            }
-            PairGeo cur = {};
-            int cli = 0, clj = 0;
-            bool cval = false;
-            if (l <= top) {
-                const int e = b0 + lane;
-                cval = e < (int)(s_off[l] + s_hist[l]);
-                if (cval) fd_gather(s_sorted, s_gidx, q, rho, wdr, n, e, cli, clj, cur);
-            }
-            while (l <= top) {
-                int nl = l, nb = b0 + 64;
-                while (nl <= top && nb >= (int)(s_off[nl] + s_hist[nl])) {
-                    ++nl;
-                    if (nl <= top) nb = (int)s_off[nl];
+            // the step after (l, b): next 64 entries of level l, else the
+            // first entry of the next non-empty level (l > top: none)
+            auto advance = [&](int &l, int &b) {
+                b += 64;
+                while (l <= top && b >= (int)(s_off[l] + s_hist[l])) {
+                    ++l;
+                    if (l <= top) b = (int)s_off[l];
                 }
-                PairGeo nxt = {};
-                int nli = 0, nlj = 0;
-                bool nval = false;
-                if (nl <= top) {
-                    const int e = nb + lane;
-                    nval = e < (int)(s_off[nl] + s_hist[nl]);
-                    if (nval) fd_gather(s_sorted, s_gidx, q, rho, wdr, n, e, nli, nlj, nxt);
+            };
+            auto fetch = [&](int l, int b, int &li, int &lj, PairGeo &g) {
+                bool v = false;
+                if (l <= top) {
+                    const int e = b + lane;
+                    v = e < (int)(s_off[l] + s_hist[l]);
+                    if (v) fd_gather(s_sorted, s_gidx, q, rho, wdr, n, e, li, lj, g);
                 }
-                if (cval) fd_pair<FAST>(P, dt, cli, clj, cur, s_p, CP, s_eps, cnt, negeps);
+                return v;
+            };
+            int l0 = lo, b0 = (int)s_off[lo] - 64;
+            advance(l0, b0);
+            int l1 = l0, b1 = b0;
+            advance(l1, b1);
+            PairGeo g0 = {}, g1 = {};
+            int li0 = 0, lj0 = 0, li1 = 0, lj1 = 0;
+            bool v0 = fetch(l0, b0, li0, lj0, g0);
+            bool v1 = fetch(l1, b1, li1, lj1, g1);
+            while (l0 <= top) {
+                int l2 = l1, b2 = b1;
+                advance(l2, b2);
+                PairGeo g2 = {};
+                int li2 = 0, lj2 = 0;
+                const bool v2 = fetch(l2, b2, li2, lj2, g2);
+                if (v0) fd_pair<FAST>(P, dt, li0, lj0, g0, s_p, CP, s_eps, cnt, negeps);
                 __syncthreads();
-                cur = nxt;
-                cli = nli;
-                clj = nlj;
-                cval = nval;
-                l = nl;
-                b0 = nb;
+                g0 = g1;
+                li0 = li1;
+                lj0 = lj1;
+                v0 = v1;
+                l0 = l1;
+                g1 = g2;
+                li1 = li2;
+                lj1 = lj2;
+                v1 = v2;
+                l1 = l2;
+                b1 = b2;
             }
             lo = hi + 1;
             if (!oversized) break;

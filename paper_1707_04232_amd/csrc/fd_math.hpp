@@ -97,24 +97,37 @@ struct FdCount {
 };
 
 // Read-only data of one oriented pair (i = smaller id): positions,
-// densities and its random draws (Gaussian vector and log of the uniform),
-// gathered from global memory one level step ahead of its use.
+// densities and its random draws (Gaussian vector and uniform), gathered
+// from global memory one level step ahead of its use.
 struct PairGeo {
     double xi, yi, zi, xj, yj, zj, rho_i, rho_j;
-    double G0, G1, G2, lnU;
+    double G0, G1, G2, U;
 };
 
-// The draws of the pair (id_i < id_j) as stored for the sweep: G1, G2, G3, ln U
-__device__ __forceinline__ void pair_draws_log(const DevParams &P, uint32_t step, uint32_t id_i,
-                                               uint32_t id_j, double out[4])
+// The draws of the pair (id_i < id_j) as stored for the sweep: G1, G2, G3, U
+__device__ __forceinline__ void pair_draws_stored(const DevParams &P, uint32_t step,
+                                                  uint32_t id_i, uint32_t id_j, double out[4])
 {
     double G[3], U;
     pair_draws(P, step, id_i, id_j, G, U);
     out[0] = G[0];
     out[1] = G[1];
     out[2] = G[2];
-    out[3] = fd_log(U);
+    out[3] = U;
 }
+
+// x - x^2/2 + x^3/3.  For |x| <= 1/2 the alternating series of log(1 + x)
+// puts log(1 + x) within x^4/2 of it (the tail after the cubic term is at
+// most |x|^4 / (4 (1 - |x|))).
+__device__ __forceinline__ double log1p_cubic(double x)
+{
+    return x * (1.0 + x * (-0.5 + x * 0.3333333333333333));
+}
+
+// Brackets closer than this are decided with the logarithms evaluated: it
+// covers the 1e-9 window in which a decision counts as marginal plus the
+// rounding of both evaluations (below 1e-13 for the values that occur).
+constexpr double kLazyMargin = 2e-9;
 
 // One pair update; li has the smaller id.  Momenta (x, y, z planes at
 // stride ps) and energies are LDS-resident.
@@ -186,20 +199,55 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
             const double quad = wpar * wpar * fast_rcp(g.b2_par)
                                 + (wqx * wqx + wqy * wqy + wqz * wqz) * fast_rcp(g.b2_perp);
             const double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
-            // log|B(v)| - log|B(v')| = (1/2) log(b_par^2 b_perp^4 / (b'_par^2 b'_perp^4))
-            const double logdet = 0.5 * fd_log((f.b2_par * f.b2_perp * f.b2_perp)
-                                            * fast_rcp(g.b2_par * g.b2_perp * g.b2_perp));
+            const double A = 0.5 * G2 - 0.5 * quad;
+            // log|B(v)| - log|B(v')| = (1/2) log Dr, Dr = b_par^2 b_perp^4 / (b'_par^2 b'_perp^4)
+            const double Dr = (f.b2_par * f.b2_perp * f.b2_perp)
+                              * fast_rcp(g.b2_par * g.b2_perp * g.b2_perp);
             // ideal gas: sum_k (S(eps'_k) - S(eps_k))/kB - log T(eps'_k) + log T(eps_k)
-            //          = (Cv/kB - 1) log((1 - delta/ei)(1 - delta/ej))
+            //          = (Cv/kB - 1) log(1 + w), 1 + w = (1 - delta/ei)(1 - delta/ej)
             const double inv_eiej = fast_rcp(ei * ej);
             const double ui = -delta * ej * inv_eiej, uj = -delta * ei * inv_eiej;
-            const double ent = P.ent_c * fd_log1p(ui + uj + ui * uj);
-            const double a = 0.5 * G2 - 0.5 * quad + logdet + ent;
-            const double lnU = pg.lnU;
-            if (fabs(a - lnU) <= 1e-9) cnt.marginal += 1;
-            if (!(lnU <= a)) {                       // reject iff U > exp(a)
-                accept = false;
-                cnt.rej_ratio += 1;
+            const double w = ui + uj + ui * uj;
+            const double U = pg.U;
+            // a = A + logdet + ent is compared with log U (reject iff U > exp(a)).
+            // Both are first bracketed with the cubic bounds of log1p_cubic;
+            // the logarithms are evaluated only when the brackets come within
+            // kLazyMargin of each other, which keeps every decision and the
+            // marginal count equal to those of the evaluated comparison.
+            bool evaluate = true;
+            const double xd = Dr - 1.0, xu = U - 1.0;
+            if (fabs(xd) <= 0.5 && fabs(w) <= 0.5) {
+                const double xd2 = xd * xd, w2 = w * w;
+                const double am = A + 0.5 * log1p_cubic(xd) + P.ent_c * log1p_cubic(w);
+                const double ar = 0.25 * xd2 * xd2 + 0.5 * fabs(P.ent_c) * w2 * w2;
+                double lu_lo, lu_hi;
+                if (xu >= -0.5) {
+                    const double xu2 = xu * xu;
+                    const double um = log1p_cubic(xu);
+                    lu_lo = um - 0.5 * xu2 * xu2;
+                    lu_hi = um + 0.5 * xu2 * xu2;
+                } else {   // U < 1/2: log U < log(1/2) < -0.69
+                    lu_lo = -INFINITY;
+                    lu_hi = -0.69;
+                }
+                if (lu_hi < am - ar - kLazyMargin) {
+                    evaluate = false;                // log U < a: accept
+                } else if (lu_lo > am + ar + kLazyMargin) {
+                    evaluate = false;                // log U > a: reject
+                    accept = false;
+                    cnt.rej_ratio += 1;
+                }
+            }
+            if (evaluate) {
+                const double logdet = 0.5 * fd_log(Dr);
+                const double ent = P.ent_c * fd_log1p(w);
+                const double a = A + logdet + ent;
+                const double lnU = fd_log(U);
+                if (fabs(a - lnU) <= 1e-9) cnt.marginal += 1;
+                if (!(lnU <= a)) {
+                    accept = false;
+                    cnt.rej_ratio += 1;
+                }
             }
         }
     }
