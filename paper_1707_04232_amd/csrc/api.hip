@@ -1,5 +1,6 @@
 // C ABI of libsdpd: parameter checks, workspace, launch order, errors.
 #include <math.h>
+#include <algorithm>
 #include <string.h>
 
 #include <new>
@@ -130,6 +131,9 @@ static void derive(const sdpd_params *P, const int nc[3], DevParams &d)
     d.m_f = (float)P->m;
     d.cW_f = (float)d.cW;
     d.cF_f = (float)d.cF;
+    d.div_per = make_fastdiv((uint32_t)std::max<int64_t>(d.ncell / 8, 1));
+    d.div_hx = make_fastdiv((uint32_t)std::max(nc[0] / 2, 1));
+    d.div_hy = make_fastdiv((uint32_t)std::max(nc[1] / 2, 1));
 }
 
 template <typename T>

@@ -44,14 +44,13 @@ __device__ __forceinline__ TaskCells task_cells(const DevParams &P, int64_t T64)
         r.phase = 0;
         return r;
     }
-    const uint32_t per = ncell / 8u, u = T - ncell;
-    const uint32_t pq = u / per;
-    const uint32_t t = u - pq * per;
+    const uint32_t u = T - ncell;
+    const uint32_t pq = fast_div(P.div_per, u);
+    const uint32_t t = u - pq * P.div_per.d;
     const int p = 1 + (int)pq;
     const int o = (p - 1) / 8, pi = (p - 1) % 8, k = 14 + o;
-    const uint32_t hx = (uint32_t)P.nc[0] / 2u, hy = (uint32_t)P.nc[1] / 2u;
-    const uint32_t txy = t / hx, tx = t - txy * hx;
-    const uint32_t tz = txy / hy, ty = txy - tz * hy;
+    const uint32_t txy = fast_div(P.div_hx, t), tx = t - txy * P.div_hx.d;
+    const uint32_t tz = fast_div(P.div_hy, txy), ty = txy - tz * P.div_hy.d;
     const int ax = 2 * (int)tx + (pi & 1), ay = 2 * (int)ty + ((pi >> 1) & 1),
               az = 2 * (int)tz + (pi >> 2);
     int bx = ax + k % 3 - 1, by = ay + (k / 3) % 3 - 1, bz = az + k / 9 - 1;
@@ -65,29 +64,47 @@ __device__ __forceinline__ TaskCells task_cells(const DevParams &P, int64_t T64)
     return r;
 }
 
-// pairs and participating particles of every task (one thread per task)
-__global__ void k_task_count(const DevParams *__restrict__ Pp,
-                             const uint32_t *__restrict__ cell_start,
-                             const uint64_t *__restrict__ masks, uint32_t *tcount, uint32_t *tnp)
+// pairs and participating particles of every task: one 32-lane half-wave
+// per task, lane x reading the masks of slots x, x + 32 of cell A, then
+// sums and ORs over the half-wave (all mask loads of a task in flight at once)
+constexpr int COUNT_WAVES = 4;   // waves per workgroup, two tasks per wave
+
+__global__ __launch_bounds__(64 * COUNT_WAVES) void k_task_count(
+    const DevParams *__restrict__ Pp, const uint32_t *__restrict__ cell_start,
+    const uint64_t *__restrict__ masks, uint32_t *tcount, uint32_t *tnp)
 {
     const DevParams &P = *Pp;
-    const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (T >= (int64_t)NMASK * P.ncell) return;
-    const TaskCells tc = task_cells(P, T);
-    const uint32_t sA = cell_start[tc.A], nA = cell_start[tc.A + 1] - sA;
-    const uint32_t nB = cell_start[tc.B + 1] - cell_start[tc.B];
+    const int lane = threadIdx.x & 63, x = lane & 31;
+    const int64_t T = ((int64_t)blockIdx.x * COUNT_WAVES + (threadIdx.x >> 6)) * 2 + (lane >> 5);
+    const bool ok = T < (int64_t)NMASK * P.ncell;
     uint32_t c = 0, na = 0;
     uint64_t orb = 0;
-    if (nA <= (uint32_t)P.cap && nB <= (uint32_t)P.cap) {
-        for (uint32_t a = 0; a < nA; ++a) {
-            const uint64_t m = masks[(int64_t)(OWN_NB + tc.slot) * P.n + sA + a];
-            na += m != 0ull;
-            orb |= m;
-            c += (uint32_t)__popcll(tc.slot == 0 ? (m & ~((2ull << a) - 1ull)) : m);
+    int slot = 0;
+    if (ok) {
+        const TaskCells tc = task_cells(P, T);
+        slot = tc.slot;
+        const uint32_t sA = cell_start[tc.A], nA = cell_start[tc.A + 1] - sA;
+        const uint32_t nB = cell_start[tc.B + 1] - cell_start[tc.B];
+        if (nA <= (uint32_t)P.cap && nB <= (uint32_t)P.cap) {
+            for (uint32_t a = (uint32_t)x; a < nA; a += 32) {
+                const uint64_t m = masks[(int64_t)(OWN_NB + tc.slot) * P.n + sA + a];
+                na += m != 0ull;
+                orb |= m;
+                c += (uint32_t)__popcll(tc.slot == 0 ? (m & ~((2ull << a) - 1ull)) : m);
+            }
         }
     }
-    tcount[T] = c;
-    tnp[T] = na + (tc.slot == 0 ? 0u : (uint32_t)__popcll(orb));
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {   // stays inside the half-wave
+        c += (uint32_t)__shfl_xor((int)c, off);
+        na += (uint32_t)__shfl_xor((int)na, off);
+        orb |= (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)orb, off) |
+               ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(orb >> 32), off) << 32);
+    }
+    if (ok && x == 0) {
+        tcount[T] = c;
+        tnp[T] = na + (slot == 0 ? 0u : (uint32_t)__popcll(orb));
+    }
 }
 
 struct TaskSpan {
@@ -257,8 +274,9 @@ int run_schedule(sdpd_ctx *c)
 {
     const int64_t ntask = (int64_t)NMASK * c->ncell;
     timer_begin(c, TK_SCHED);
-    hipLaunchKernelGGL(k_task_count, dim3((unsigned)((ntask + 255) / 256)), dim3(256), 0, c->stream,
-                       c->dparams, c->cell_start, c->masks, c->task_count, c->task_np);
+    const int64_t count_blocks = (ntask + 2 * COUNT_WAVES - 1) / (2 * COUNT_WAVES);
+    hipLaunchKernelGGL(k_task_count, dim3((unsigned)count_blocks), dim3(64 * COUNT_WAVES), 0,
+                       c->stream, c->dparams, c->cell_start, c->masks, c->task_count, c->task_np);
     int rc = check_hip(hipGetLastError());
     if (rc) return rc;
     if ((rc = run_scan(c, c->task_count, c->pair_off, ntask, c->block_sums, -1))) return rc;

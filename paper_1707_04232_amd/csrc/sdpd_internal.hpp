@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "sdpd.h"
+#include "fastdiv.hpp"
 
 namespace sdpd {
 
@@ -54,6 +55,9 @@ struct DevParams {
     int mixed;
     float cell_f[3];        // cell edge lengths box / nc
     float h_f, h2_f, inv_h_f, m_f, cW_f, cF_f;
+    // task numbering of the F/D schedule: tasks per inter-cell phase
+    // (ncell / 8) and the half extents nc[0] / 2, nc[1] / 2
+    FastDiv div_per, div_hx, div_hy;
 };
 
 // observable record (doubles): E, Eint, KE, P0, P1, P2, min_eps, then the
