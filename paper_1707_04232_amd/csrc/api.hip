@@ -148,9 +148,9 @@ static void free_ctx(sdpd_ctx *c)
 {
     void *bufs[] = {c->cell_of, c->count, c->cursor, c->cell_start, c->block_sums, c->tmp_idx,
                     c->perm, c->cell_sorted, c->tq, c->tp, c->teps, c->trho, c->tf, c->tid,
-                    c->pi, c->masks, c->counters, c->err, c->obs_partial, c->obs_out,
+                    c->masks, c->counters, c->err, c->obs_partial, c->obs_out,
                     c->dparams, c->task_count, c->task_np, c->pair_off, c->part_off,
-                    c->part_list, c->pairs, c->draws, c->qr, c->pi_f, c->dstep};
+                    c->part_list, c->pairs, c->draws, c->qr, c->pi_f, c->dstep, c->q4};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
@@ -283,7 +283,7 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     rc = rc ? rc : dalloc(&c->teps, n);
     rc = rc ? rc : dalloc(&c->trho, n);
     rc = rc ? rc : dalloc(&c->tid, n);
-    rc = rc ? rc : dalloc(&c->pi, n);
+    rc = rc ? rc : dalloc(&c->q4, 4 * n);
     if (c->dp.mixed) {
         rc = rc ? rc : dalloc(&c->qr, 3 * n);
         rc = rc ? rc : dalloc(&c->pi_f, n);

@@ -183,7 +183,7 @@ __global__ void k_gather(DevParams P, int64_t n, const uint32_t *perm, const uin
                          const double *q, const double *p, const double *eps, const double *rho,
                          const double *f, const uint32_t *id, double *tq, double *tp,
                          double *teps, double *trho, double *tf, uint32_t *tid,
-                         uint32_t *cell_sorted, float *qr)
+                         uint32_t *cell_sorted, float *qr, double *q4)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -196,6 +196,9 @@ __global__ void k_gather(DevParams P, int64_t n, const uint32_t *perm, const uin
         for (int d = 0; d < 3; ++d)
             qr[d * n + k] = (float)(q[d * n + i] - (double)cc[d] * (P.box[d] / P.nc[d]));
     }
+    q4[4 * k] = q[i];
+    q4[4 * k + 1] = q[n + i];
+    q4[4 * k + 2] = q[2 * n + i];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         tq[c * n + k] = q[c * n + i];
@@ -258,7 +261,7 @@ int run_build_cells(sdpd_ctx *c, const sdpd_state *s, int kick_drift)
                            c->cell_start, s->id, c->perm, n, c->prm.cell_cap);
         hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, c->dp, n, c->perm,
                            c->cell_of, s->q, s->p, s->eps, s->rho, s->f, s->id, c->tq, c->tp,
-                           c->teps, c->trho, c->tf, c->tid, c->cell_sorted, c->qr);
+                           c->teps, c->trho, c->tf, c->tid, c->cell_sorted, c->qr, c->q4);
         if ((rc = check_hip(hipGetLastError()))) return rc;
         const size_t d3 = sizeof(double) * 3 * (size_t)n, d1 = sizeof(double) * (size_t)n;
         if ((rc = check_hip(hipMemcpyAsync(s->q, c->tq, d3, hipMemcpyDeviceToDevice, c->stream))))

@@ -1,6 +1,7 @@
 // SPH density, eq. (sdpd-rho-v), the entropy-conserving energy update of
 // Sec. 3.1, and the active-pair masks of the fluctuation/dissipation sweep.
 #include "sdpd_internal.hpp"
+#include "fd_elem.hpp"
 
 namespace sdpd {
 
@@ -15,7 +16,8 @@ __device__ __forceinline__ double kernel_w(const DevParams &P, double r)
     return 2.0 * P.cW * (t * t * t);
 }
 
-// One thread per particle in cell order.  Candidates are the particles of
+// One thread per particle in cell order, positions read from the packed
+// (x, y, z, .) records the cell pass writes.  Candidates are the particles of
 // the 27 cells around the particle's cell, visited in the fixed order
 // (offset index k = 0..26 with z slowest, then slot), so the sum is
 // deterministic.  The periodic image is chosen per neighbour cell: a cell
@@ -24,7 +26,7 @@ __device__ __forceinline__ double kernel_w(const DevParams &P, double r)
 // closer than h (L >= 4 h), in the same rounding as the plain form.  For all
 // 27 cells the bit of every active partner's slot is stored in
 // masks[k * n + i] (the own cell, k = 13, without i itself).
-__global__ __launch_bounds__(256) void k_density(DevParams P, const double *__restrict__ q,
+__global__ __launch_bounds__(256) void k_density(DevParams P, const double *__restrict__ q4,
                                                  const uint32_t *__restrict__ cell_sorted,
                                                  const uint32_t *__restrict__ cell_start,
                                                  double *rho, double *eps, int update_eps,
@@ -38,7 +40,7 @@ __global__ __launch_bounds__(256) void k_density(DevParams P, const double *__re
     const int cx = (int)(c % (uint32_t)P.nc[0]);
     const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
     const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
-    const double xi = q[i], yi = q[n + i], zi = q[2 * n + i];
+    const double xi = q4[4 * i], yi = q4[4 * i + 1], zi = q4[4 * i + 2];
     double acc = 0.0;
     for (int k = 0; k < 27; ++k) {
         const NbCell nb = neighbour_cell(P, cx, cy, cz, k);
@@ -49,16 +51,19 @@ __global__ __launch_bounds__(256) void k_density(DevParams P, const double *__re
             masks[(int64_t)k * n + i] = 0ull;
             continue;
         }
-        for (uint32_t j = s; j < e; ++j) {
-            const double dx = (xi - q[j]) + nb.sx;
-            const double dy = (yi - q[n + j]) + nb.sy;
-            const double dz = (zi - q[2 * n + j]) + nb.sz;
+        uint64_t bit = 1ull;   // slot bit of candidate j
+        for (uint32_t j = s; j < e; ++j, bit <<= 1) {
+            const double2 xy = *reinterpret_cast<const double2 *>(q4 + 4 * (int64_t)j);
+            const double dx = (xi - xy.x) + nb.sx;
+            const double dy = (yi - xy.y) + nb.sy;
+            const double dz = (zi - q4[4 * (int64_t)j + 2]) + nb.sz;
             const double r2 = dx * dx + dy * dy + dz * dz;
             if (r2 < P.h2) {
-                acc += P.m * kernel_w(P, sqrt(r2));
-                if (j != (uint32_t)i) mask |= 1ull << (j - s);
+                acc += P.m * kernel_w(P, r2 > 0.0 ? fd_sqrt(r2) : 0.0);   // r = 0: i itself
+                mask |= bit;
             }
         }
+        if (k == OWN_NB) mask &= ~(1ull << (i - (int64_t)s));   // i itself is no partner
         masks[(int64_t)k * n + i] = mask;
     }
     const double rho_old = rho[i];
@@ -83,7 +88,7 @@ int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps)
     }
     timer_begin(c, TK_DENSITY);
     hipLaunchKernelGGL(k_density, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, c->stream,
-                       c->dp, s->q, c->cell_sorted, c->cell_start, s->rho, s->eps, update_eps,
+                       c->dp, c->q4, c->cell_sorted, c->cell_start, s->rho, s->eps, update_eps,
                        c->masks, c->err);
     int rc = check_hip(hipGetLastError());
     timer_end(c, TK_DENSITY);

@@ -1,7 +1,9 @@
-// Compact FP64 elementary functions for the fluctuation/dissipation update.
+// Compact FP64 elementary functions for the fluctuation/dissipation update
+// and the particle passes (pair distances).
 //
 // Their arguments are always positive, finite and well ranged (uniform draws
-// in (0, 1), energies, ratios of friction amplitudes), so the special-case
+// in (0, 1), energies, ratios of friction amplitudes, squared distances
+// below h^2; a zero distance is handled by the caller), so the special-case
 // handling of a general math library is not needed.  Accuracy: a few ulp,
 // far below the 1e-10 agreement required with the FP64 oracle.
 //   * log: x = m 2^e with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(f),

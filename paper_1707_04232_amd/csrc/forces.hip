@@ -1,6 +1,7 @@
 // Conservative pressure forces, eq. (cons-forces), fused with the second
 // half kick of eq. (sdpd-verlet); observables (Sec. 2.2.1).
 #include "sdpd_internal.hpp"
+#include "fd_elem.hpp"
 
 namespace sdpd {
 
@@ -16,19 +17,27 @@ __device__ __forceinline__ double kernel_f(const DevParams &P, double r)
 }
 
 // P_i / rho_i^2 from the ideal-gas closure: A kB rho eps / (m Cv) / rho^2
-__global__ void k_pressure_term(DevParams P, const double *eps, const double *rho, double *pi)
+// Pi_i = P_i / rho_i^2, stored with the position as (x, y, z, Pi) so that
+// the force pass reads one 32-byte record per partner
+__global__ void k_pressure_term(DevParams P, const double *q, const double *eps,
+                                const double *rho, double *q4)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < P.n) pi[i] = P.cPi * eps[i] / rho[i];
+    if (i >= P.n) return;
+    const double v = P.cPi * eps[i] / rho[i];
+    double4 r;
+    r.x = q[i];
+    r.y = q[P.n + i];
+    r.z = q[2 * P.n + i];
+    r.w = v;
+    reinterpret_cast<double4 *>(q4)[i] = r;
 }
 
 // f_i = sum_{j != i, r < h} m^2 (Pi_i + Pi_j) F_ij r_ij over the partners
 // recorded in the 27 active-pair masks of the density pass (same positions),
 // in the fixed order (offset index, then slot); optionally p_i += dt/2 f_i.
-// The masks are read first (27 independent loads), then the set bits are
-// visited as one flat sequence.
-__global__ __launch_bounds__(256) void k_forces(DevParams P, const double *__restrict__ q,
-                                                const double *__restrict__ pi,
+// Only the set bits of each mask are visited.
+__global__ __launch_bounds__(256) void k_forces(DevParams P, const double *__restrict__ q4,
                                                 const uint32_t *__restrict__ cell_sorted,
                                                 const uint32_t *__restrict__ cell_start,
                                                 const uint64_t *__restrict__ masks,
@@ -41,8 +50,8 @@ __global__ __launch_bounds__(256) void k_forces(DevParams P, const double *__res
     const int cx = (int)(c % (uint32_t)P.nc[0]);
     const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
     const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
-    const double xi = q[i], yi = q[n + i], zi = q[2 * n + i];
-    const double pii = pi[i];
+    const double4 qi = reinterpret_cast<const double4 *>(q4)[i];
+    const double xi = qi.x, yi = qi.y, zi = qi.z, pii = qi.w;
     const double m2 = P.m * P.m;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     for (int k = 0; k < 27; ++k) {
@@ -53,11 +62,12 @@ __global__ __launch_bounds__(256) void k_forces(DevParams P, const double *__res
         while (mask) {
             const uint32_t j = s + (uint32_t)__builtin_ctzll(mask);
             mask &= mask - 1ull;
-            const double dx = (xi - q[j]) + nb.sx;
-            const double dy = (yi - q[n + j]) + nb.sy;
-            const double dz = (zi - q[2 * n + j]) + nb.sz;
+            const double4 qj = reinterpret_cast<const double4 *>(q4)[j];
+            const double dx = (xi - qj.x) + nb.sx;
+            const double dy = (yi - qj.y) + nb.sy;
+            const double dz = (zi - qj.z) + nb.sz;
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const double sc = m2 * (pii + pi[j]) * kernel_f(P, sqrt(r2));
+            const double sc = m2 * (pii + qj.w) * kernel_f(P, r2 > 0.0 ? fd_sqrt(r2) : 0.0);
             fx += sc * dx;
             fy += sc * dy;
             fz += sc * dz;
@@ -80,9 +90,9 @@ int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick)
     if (c->dp.mixed) return run_forces_f32(c, s, half_kick);
     const unsigned g = (unsigned)((c->n + 255) / 256);
     timer_begin(c, TK_FORCE);
-    hipLaunchKernelGGL(k_pressure_term, dim3(g), dim3(256), 0, c->stream, c->dp, s->eps, s->rho,
-                       c->pi);
-    hipLaunchKernelGGL(k_forces, dim3(g), dim3(256), 0, c->stream, c->dp, s->q, c->pi,
+    hipLaunchKernelGGL(k_pressure_term, dim3(g), dim3(256), 0, c->stream, c->dp, s->q, s->eps,
+                       s->rho, c->q4);
+    hipLaunchKernelGGL(k_forces, dim3(g), dim3(256), 0, c->stream, c->dp, c->q4,
                        c->cell_sorted, c->cell_start, c->masks, s->f, s->p, half_kick);
     int rc = check_hip(hipGetLastError());
     timer_end(c, TK_FORCE);

@@ -88,7 +88,7 @@ struct sdpd_ctx {
     // gather targets of the sort (same shapes as the state)
     double *tq, *tp, *teps, *trho, *tf;
     uint32_t *tid;
-    double *pi;                  // P/rho^2 per particle
+    double *q4;                  // (x, y, z, P/rho^2) per particle in cell order, 32 B
     float *qr, *pi_f;            // mixed precision: positions relative to the cell, P/rho^2
     uint64_t *masks;             // NNB * n
     unsigned long long *counters;

@@ -89,6 +89,24 @@ def test_density_and_forces(case, kernel):
     compare_state(S.to_numpy(), R, 1e-12, keys=("rho", "f"))
 
 
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_density_and_forces_coincident_particles(kernel):
+    """Degenerate geometry: two distinct particles at one position (r = 0).
+    The pair adds W(0) to both densities and, with r_ij = 0, nothing to the
+    forces; the other partners are unaffected."""
+    q, p, eps, ids = uniform_state(400, (10.0, 10.0, 10.0), seed=5)
+    q[:, 7] = q[:, 3]
+    say("density/forces coincident pair, kernel", kernel)
+    gp, op, S, R = both(q, p, eps, ids, 10.0, kernel=kernel, Cv=1.5)
+    with sd().Context(gp) as ctx:
+        ctx.prepare(S)
+        ctx.sync()
+    O.prepare(op, R)
+    g = S.to_numpy()
+    assert np.all(np.isfinite(g["rho"])) and np.all(np.isfinite(g["f"]))
+    compare_state(g, R, 1e-12, keys=("rho", "f"))
+
+
 def test_density_constant_entropy_update():
     import torch
     q, p, eps, ids = lattice_state(12, Cv=1.5, T=0.1)
