@@ -19,9 +19,10 @@
 // momenta and energies of the particles that take part in a pair, sorts the
 // range's pairs by level and applies the pairs of one level (which share no
 // particle) as parallel steps of 64 lanes.  Positions, densities and ids do
-// not change during the sweep: they are read from global memory, one level
-// step ahead of their use, which keeps the LDS footprint at 36 B per
-// particle and leaves room for more resident waves.  The random draws of a
+// not change during the sweep: positions and densities are packed once per
+// sweep into one (x, y, z, rho) record per particle and read from global
+// memory two level steps ahead of their use, which keeps the LDS footprint
+// at 36 B per particle and leaves room for more resident waves.  The random draws of a
 // pair depend only on (step, ids): after the level sort they are computed for
 // all of the batch's pairs at full lane occupancy (which also orients every
 // pair, i = smaller id) and stored in sorted order in a global buffer, from
@@ -68,26 +69,25 @@ __host__ __device__ inline size_t fd_lds_bytes(int cap_p, int cap_e)
 constexpr uint64_t POS_MASK = (1ull << 25) - 1ull;   // list position field of a pair entry
 
 // read-only data of the (oriented) pair at sorted position e: batch particle
-// indices from the LDS list, then positions, densities and the stored draws;
-// loads are issued, not waited for
+// indices from the LDS list, then the (x, y, z, rho) records of both
+// particles and the stored draws; loads are issued, not waited for
 __device__ __forceinline__ void fd_gather(const uint32_t *s_sorted, const uint32_t *s_gidx,
-                                          const double *__restrict__ q,
-                                          const double *__restrict__ rho,
-                                          const double *__restrict__ draws, int64_t n, int e,
+                                          const double4 *__restrict__ qrho,
+                                          const double *__restrict__ draws, int e,
                                           int &li, int &lj, PairGeo &g)
 {
     const uint32_t pr = s_sorted[e];
     li = (int)(pr & 0xFFFFu);
     lj = (int)(pr >> 16);
-    const int64_t gi = s_gidx[li], gj = s_gidx[lj];
-    g.xi = q[gi];
-    g.yi = q[n + gi];
-    g.zi = q[2 * n + gi];
-    g.xj = q[gj];
-    g.yj = q[n + gj];
-    g.zj = q[2 * n + gj];
-    g.rho_i = rho[gi];
-    g.rho_j = rho[gj];
+    const double4 a = qrho[s_gidx[li]], b = qrho[s_gidx[lj]];
+    g.xi = a.x;
+    g.yi = a.y;
+    g.zi = a.z;
+    g.rho_i = a.w;
+    g.xj = b.x;
+    g.yj = b.y;
+    g.zj = b.z;
+    g.rho_j = b.w;
     const double2 *d = reinterpret_cast<const double2 *>(draws) + 2 * (int64_t)e;
     const double2 d01 = d[0], d23 = d[1];
     g.G0 = d01.x;
@@ -99,9 +99,8 @@ __device__ __forceinline__ void fd_gather(const uint32_t *s_sorted, const uint32
 // FAST: the common case (EMS, Lucy kernel, zeta = 0) fixed at compile time
 template <bool FAST>
 __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ Pp, FdLaunch L,
-                                                 const double *__restrict__ q, double *p,
-                                                 double *eps, const double *__restrict__ rho,
-                                                 const uint32_t *__restrict__ id,
+                                                 const double4 *__restrict__ qrho, double *p,
+                                                 double *eps, const uint32_t *__restrict__ id,
                                                  const uint32_t *__restrict__ pair_off,
                                                  const uint32_t *__restrict__ part_off,
                                                  const uint64_t *__restrict__ pairs,
@@ -339,7 +338,7 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                 if (l <= top) {
                     const int e = b + lane;
                     v = e < (int)(s_off[l] + s_hist[l]);
-                    if (v) fd_gather(s_sorted, s_gidx, q, rho, wdr, n, e, li, lj, g);
+                    if (v) fd_gather(s_sorted, s_gidx, qrho, wdr, e, li, lj, g);
                 }
                 return v;
             };
@@ -530,11 +529,26 @@ static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, in
                       c->dp.par_twice_perp;
     auto kern = fast ? k_fd_phase<true> : k_fd_phase<false>;
     hipLaunchKernelGGL(kern, dim3((unsigned)wg), dim3(64), lds, c->stream, c->dparams, L,
-                       s->q, s->p, s->eps, s->rho, s->id, c->pair_off, c->part_off, c->pairs,
+                       reinterpret_cast<const double4 *>(c->q4), s->p, s->eps, s->id,
+                       c->pair_off, c->part_off, c->pairs,
                        c->part_list, (uint32_t)c->pair_cap, (uint32_t)c->part_cap,
                        c->dstep, dt_fd, c->draws, c->counters, c->err);
     timer_end(c, TK_FD);
     return check_hip(hipGetLastError());
+}
+
+// (x, y, z, rho) record of every particle for the pair gathers of the sweep
+__global__ void k_pack_qrho(int64_t n, const double *__restrict__ q,
+                            const double *__restrict__ rho, double4 *qrho)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double4 r;
+    r.x = q[i];
+    r.y = q[n + i];
+    r.z = q[2 * n + i];
+    r.w = rho[i];
+    qrho[i] = r;
 }
 
 // The step index of the draws is read from c->dstep on the device (set by
@@ -544,6 +558,11 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
     if (c->prm.fd == SDPD_FD_NONE || c->n == 0) return SDPD_OK;
     int rc = run_schedule(c);
     if (rc) return rc;
+    timer_begin(c, TK_FD);
+    hipLaunchKernelGGL(k_pack_qrho, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, c->stream,
+                       c->n, s->q, s->rho, reinterpret_cast<double4 *>(c->q4));
+    timer_end(c, TK_FD);
+    if ((rc = check_hip(hipGetLastError()))) return rc;
     c->fd_swept = 1;
     const int zero = 0;
     if ((rc = launch_phases(c, s, &zero, 1, dt_fd))) return rc;
