@@ -558,10 +558,10 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
     if (c->prm.fd == SDPD_FD_NONE || c->n == 0) return SDPD_OK;
     int rc = run_schedule(c);
     if (rc) return rc;
-    timer_begin(c, TK_FD);
+    timer_begin(c, TK_SCHED);   // sweep preparation, with the schedule
     hipLaunchKernelGGL(k_pack_qrho, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, c->stream,
                        c->n, s->q, s->rho, reinterpret_cast<double4 *>(c->q4));
-    timer_end(c, TK_FD);
+    timer_end(c, TK_SCHED);
     if ((rc = check_hip(hipGetLastError()))) return rc;
     c->fd_swept = 1;
     const int zero = 0;
