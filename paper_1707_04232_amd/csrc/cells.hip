@@ -22,6 +22,28 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
 // Half kick and drift of the Velocity-Verlet scheme, eq. (sdpd-verlet),
 // fused with the cell assignment:  p += dt/2 f;  q += dt p / m wrapped once
 // into [0, box);  cell = cx + nx (cy + ny cz).
+// ctr[key] += 1 for every active lane with one atomic per distinct key of
+// the wave (the state arrives nearly in cell order, so a wave holds a few
+// cells); returns the lane's position among the increments of its key
+__device__ __forceinline__ uint32_t wave_counted_inc(uint32_t *ctr, uint32_t key)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(1);
+    uint32_t pos = 0;
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const uint32_t lkey = (uint32_t)__shfl((int)key, leader);
+        const uint64_t peers = __ballot(key == lkey) & todo;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&ctr[lkey], (uint32_t)__popcll(peers));
+        base = (uint32_t)__shfl((int)base, leader);
+        if ((peers >> lane) & 1ull)
+            pos = base + (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+        todo &= ~peers;
+    }
+    return pos;
+}
+
 __global__ void k_kick_drift_assign(DevParams P, double *q, double *p, const double *f,
                                     int kick_drift, uint32_t *cell_of, uint32_t *count,
                                     uint32_t *err)
@@ -48,7 +70,7 @@ __global__ void k_kick_drift_assign(DevParams P, double *q, double *p, const dou
     if (!finite) atomicOr(err, ERR_NONFINITE);
     uint32_t c = (uint32_t)(cc[0] + P.nc[0] * (cc[1] + P.nc[1] * cc[2]));
     cell_of[i] = c;
-    atomicAdd(&count[c], 1u);
+    (void)wave_counted_inc(count, c);
 }
 
 // --- exclusive scan of the cell counts into cell_start (3 passes) ---------
@@ -148,7 +170,7 @@ __global__ void k_scatter(const uint32_t *cell_of, const uint32_t *cell_start, u
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint32_t c = cell_of[i];
-    uint32_t pos = cell_start[c] + atomicAdd(&cursor[c], 1u);
+    uint32_t pos = cell_start[c] + wave_counted_inc(cursor, c);
     tmp_idx[pos] = (uint32_t)i;
 }
 
