@@ -115,9 +115,13 @@ __device__ __forceinline__ void fd_sincospi(double t, double &s, double &c)
     const double r = t - 0.5 * k;     // exact, |r| <= 1/4
     double sr, cr;
     fd_sincospi_reduced(r, sr, cr);
+    // quarter-turn rotation as selects (no branches): odd q swaps sin and
+    // cos; sin changes sign for q = 2, 3 and cos for q = 1, 2
     const int q = ((int)k) & 3;
-    s = q == 0 ? sr : (q == 1 ? cr : (q == 2 ? -sr : -cr));
-    c = q == 0 ? cr : (q == 1 ? -sr : (q == 2 ? -cr : sr));
+    const bool sw = (q & 1) != 0;
+    const double a = sw ? cr : sr, b = sw ? sr : cr;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
 }
 
 }  // namespace sdpd
