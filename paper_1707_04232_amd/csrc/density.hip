@@ -16,6 +16,31 @@ __device__ __forceinline__ double kernel_w(const DevParams &P, double r)
     return 2.0 * P.cW * (t * t * t);
 }
 
+// Candidates of one neighbour cell [s, e): adds m W(r) to acc and returns
+// the slot bits of the partners with r < h.
+template <bool SHIFT>
+__device__ __forceinline__ uint64_t density_cell(const DevParams &P, const double *__restrict__ q4,
+                                                 uint32_t s, uint32_t e, double xi, double yi,
+                                                 double zi, const NbCell &nb, double &acc)
+{
+    uint64_t mask = 0, bit = 1ull;   // slot bit of candidate j
+    for (uint32_t j = s; j < e; ++j, bit <<= 1) {
+        const double2 xy = *reinterpret_cast<const double2 *>(q4 + 4 * (int64_t)j);
+        double dx = xi - xy.x, dy = yi - xy.y, dz = zi - q4[4 * (int64_t)j + 2];
+        if (SHIFT) {
+            dx += nb.sx;
+            dy += nb.sy;
+            dz += nb.sz;
+        }
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < P.h2) {
+            acc += P.m * kernel_w(P, r2 > 0.0 ? fd_sqrt(r2) : 0.0);   // r = 0: i itself
+            mask |= bit;
+        }
+    }
+    return mask;
+}
+
 // One thread per particle in cell order, positions read from the packed
 // (x, y, z, .) records the cell pass writes.  Candidates are the particles of
 // the 27 cells around the particle's cell, visited in the fixed order
@@ -51,18 +76,11 @@ __global__ __launch_bounds__(256) void k_density(DevParams P, const double *__re
             masks[(int64_t)k * n + i] = 0ull;
             continue;
         }
-        uint64_t bit = 1ull;   // slot bit of candidate j
-        for (uint32_t j = s; j < e; ++j, bit <<= 1) {
-            const double2 xy = *reinterpret_cast<const double2 *>(q4 + 4 * (int64_t)j);
-            const double dx = (xi - xy.x) + nb.sx;
-            const double dy = (yi - xy.y) + nb.sy;
-            const double dz = (zi - q4[4 * (int64_t)j + 2]) + nb.sz;
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < P.h2) {
-                acc += P.m * kernel_w(P, r2 > 0.0 ? fd_sqrt(r2) : 0.0);   // r = 0: i itself
-                mask |= bit;
-            }
-        }
+        // the shift adds only where a lane of the wave crosses the boundary
+        // (x + 0.0 == x, so the results do not depend on the choice)
+        const bool shifted = nb.sx != 0.0 || nb.sy != 0.0 || nb.sz != 0.0;
+        mask = __any(shifted) ? density_cell<true>(P, q4, s, e, xi, yi, zi, nb, acc)
+                              : density_cell<false>(P, q4, s, e, xi, yi, zi, nb, acc);
         if (k == OWN_NB) mask &= ~(1ull << (i - (int64_t)s));   // i itself is no partner
         masks[(int64_t)k * n + i] = mask;
     }
