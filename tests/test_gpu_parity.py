@@ -136,6 +136,10 @@ FD_CASES = [
     ("ssa_cv10", 10, 10.0, 1.0, 0.005, 2, 0, 0.0),
     ("ems_24x20x16", (24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0),
     ("ems_32", 32, 1.5, 0.1, 0.005, 0, 0, 0.0),
+    # large moves: the cubic brackets of the Metropolis test often fail and
+    # the logarithms are evaluated; Cv < kB makes the entropy factor negative
+    ("ems_cv1.5_dt5", 10, 1.5, 1.0, 5.0, 0, 0, 0.0),
+    ("ems_cv0.8_dt0.5", 10, 0.8, 1.0, 0.5, 0, 0, 0.0),
 ]
 
 
