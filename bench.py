@@ -92,14 +92,16 @@ def cpu_baseline(w, sample_dims=(64, 64, 64), nsteps=2):
 
 def replicas_bench(args):
     """Batched replicas: 256 boxes of uneven size and state, each a context of
-    its own, spread over 8 streams and advanced by one HIP graph; compared
-    with launching every box's step from the host in turn."""
+    its own, spread over args.streams streams and advanced by captured HIP
+    graphs (one per stream when the process has a hardware queue per
+    stream); compared with launching every box's step from the host in
+    turn."""
     import torch
     from paper_1707_04232_amd import sdpd
     from paper_1707_04232_amd.workload import lattice_state, replica_set
     nbox = 256
     boxes = replica_set(nbox, seed=0)
-    streams = [torch.cuda.Stream() for _ in range(8)]
+    streams = [torch.cuda.Stream() for _ in range(args.streams)]
     ctxs, states, n_tot = [], [], 0
     for b, (side, T, Cv) in enumerate(boxes):
         q, p, eps, ids = lattice_state(side, Cv=Cv, T=T, seed=b)
@@ -141,7 +143,7 @@ def replicas_bench(args):
         c.close()
     value = n_tot * args.steps / el
     out = {
-        "metric": "particle-steps/s (full SDPD step), 256 replica boxes in one HIP graph",
+        "metric": "particle-steps/s (full SDPD step), 256 replica boxes in captured HIP graphs",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -149,6 +151,7 @@ def replicas_bench(args):
         "config": {"workload": "replicas256", "boxes": nbox, "n_total": n_tot,
                    "sides": [min(b[0] for b in boxes), max(b[0] for b in boxes)],
                    "T_range": [0.1, 2.0], "Cv_range": [1.5, 50.0], "streams": len(streams),
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                    "dt": 0.005, "fd": "EMS"},
         "eager_sequential": {"value": n_tot * neager / el_eager, "steps": neager,
                              "ms_per_step": 1e3 * el_eager / neager},
@@ -239,6 +242,8 @@ def main():
     ap.add_argument("--fd-every", type=int, default=1,
                     help="F/D sweep every this many steps, with theta * dt (multiple time steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--streams", type=int, default=32,
+                    help="streams of the replicas workload (at most 32)")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket kernels with HIP events")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -251,6 +256,11 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "replicas256":
+        if not 1 <= args.streams <= 32:
+            ap.error("--streams must be in 1..32")
+        # one hardware queue per stream, set before HIP starts (HIP's default is 4)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(max(4, args.streams))
     import torch
     from paper_1707_04232_amd import sdpd
     from paper_1707_04232_amd.workload import WORKLOADS, workload_state

@@ -219,8 +219,11 @@ int sdpd_get_tuning(sdpd_ctx *ctx, sdpd_tuning *out);
  * must share the device and fd_every, have timing off, appear once, and
  * use created streams (not the null stream, which cannot be captured).
  * sdpd_batch_create captures fd_every consecutive steps of every box into
- * one HIP graph (it waits for the boxes' streams first; the graph refers to
- * the given state arrays, which must stay allocated).  sdpd_batch_run
+ * HIP graphs (it waits for the boxes' streams first; the graphs refer to
+ * the given state arrays, which must stay allocated): one graph per stream
+ * when the process has at least as many hardware queues as there are
+ * streams (environment GPU_MAX_HW_QUEUES, 4 when unset), else one graph
+ * that forks to and joins the boxes' streams.  sdpd_batch_run
  * replays it for steps step0 .. step0+nsteps-1 (both multiples of
  * fd_every): every box advances exactly as with sdpd_step on its own (bit
  * for bit), the boxes of different streams concurrently.  It is

@@ -1,11 +1,17 @@
 // Batched replicas: many independent boxes (each its own context and
-// stream) advanced together by one HIP graph.  The graph holds fd_every
-// consecutive steps of every box, captured once from the same launch
-// sequence the eager sdpd_step issues; the boxes' streams are forked from
-// and joined back into the batch's origin stream with events, so boxes run
-// concurrently while each box keeps its own launch order.  The step index
-// of the random draws lives on the device: set once per run, advanced by
-// every replayed step, so one graph serves every step block.
+// stream) advanced together by HIP graphs holding fd_every consecutive steps
+// of every box, captured once from the same launch sequence the eager
+// sdpd_step issues.  Two layouts:
+//   * one graph per stream (the boxes of that stream, replayed on it), when
+//     the process has a hardware queue for every stream (GPU_MAX_HW_QUEUES,
+//     4 unless set): the streams then run side by side;
+//   * otherwise one graph for all boxes, the boxes' streams forked from and
+//     joined back into the batch's origin stream with events.
+// Either way each box keeps its own launch order.  The step index of the
+// random draws lives on the device: set once per run, advanced by every
+// replayed step, so one capture serves every step block.
+#include <stdlib.h>
+
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -21,16 +27,31 @@ struct sdpd_batch {
     hipEvent_t fork = nullptr, done = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<hipGraph_t> sgraph;   // per-stream layout
+    std::vector<hipGraphExec_t> sexec;
     int theta = 1;
 };
+
+// hardware queues HIP gives the process (its default is 4)
+static int hw_queues()
+{
+    const char *v = getenv("GPU_MAX_HW_QUEUES");
+    const int q = v ? atoi(v) : 0;
+    return q > 0 ? q : 4;
+}
 
 using namespace sdpd;
 
 static void batch_free(sdpd_batch *b)
 {
     if (b->origin) (void)hipStreamSynchronize(b->origin);
+    for (hipStream_t st : b->streams) (void)hipStreamSynchronize(st);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipGraphExec_t e : b->sexec)
+        if (e) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t g : b->sgraph)
+        if (g) (void)hipGraphDestroy(g);
     for (hipEvent_t e : b->join)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : b->ready)
@@ -87,7 +108,36 @@ int sdpd_batch_create(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
         batch_free(b);
         return rc;
     }
-    // capture theta steps of every box
+    if (b->streams.size() > 1 && (int)b->streams.size() <= hw_queues()) {
+        // per-stream graphs: each stream captures theta steps of its boxes
+        for (size_t i = 0; !rc && i < b->streams.size(); ++i) {
+            hipStream_t st = b->streams[i];
+            if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                rc = SDPD_EHIP;
+                break;
+            }
+            for (int k = 0; !rc && k < theta; ++k)
+                for (int j = 0; !rc && j < nbox; ++j)
+                    if (b->ctx[j]->stream == st)
+                        rc = enqueue_step(b->ctx[j], &b->st[j], (uint64_t)k, false);
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(st, &g);
+            b->sgraph.push_back(g);
+            if (!rc && ec != hipSuccess) rc = SDPD_EHIP;
+            hipGraphExec_t e = nullptr;
+            if (!rc && hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess)
+                rc = SDPD_EHIP;
+            b->sexec.push_back(e);
+        }
+        if (rc) {
+            (void)hipGetLastError();
+            batch_free(b);
+            return rc;
+        }
+        *out = b;
+        return SDPD_OK;
+    }
+    // one graph: capture theta steps of every box
     if (hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         batch_free(b);
         return SDPD_EHIP;
@@ -125,6 +175,12 @@ int sdpd_batch_run(sdpd_batch *b, uint64_t step0, int nsteps)
     int rc;
     for (sdpd_ctx *c : b->ctx)
         if ((rc = launch_fill_u64(c, (unsigned long long *)c->dstep, step0, 1))) return rc;
+    if (!b->sexec.empty()) {
+        for (int r = 0; r < nsteps / b->theta; ++r)
+            for (size_t i = 0; i < b->streams.size(); ++i)
+                if ((rc = check_hip(hipGraphLaunch(b->sexec[i], b->streams[i])))) return rc;
+        return SDPD_OK;
+    }
     for (size_t i = 0; i < b->streams.size(); ++i) {
         if ((rc = check_hip(hipEventRecord(b->ready[i], b->streams[i])))) return rc;
         if ((rc = check_hip(hipStreamWaitEvent(b->origin, b->ready[i], 0)))) return rc;

@@ -67,3 +67,49 @@ def test_batch_graph_matches_eager_steps(fd_every):
                 assert ob["E"] == orf["E"]
     for c, _ in ref + bat:
         c.close()
+
+
+_PER_STREAM_CHILD = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np, torch
+from paper_1707_04232_amd import sdpd
+from tests.test_gpu_batch import _boxes
+print("[case] per-stream graphs, GPU_MAX_HW_QUEUES =", __import__("os").environ["GPU_MAX_HW_QUEUES"], flush=True)
+streams = [torch.cuda.Stream() for _ in range(3)]
+ref = _boxes(6, 1, None)
+bat = _boxes(6, 1, streams)
+torch.cuda.synchronize()
+with sdpd.Batch([c for c, _ in bat], [s for _, s in bat]) as B:
+    step = 0
+    for rep in range(3):
+        B.run(step, 2)
+        for c, S in ref:
+            c.step(S, step, 2, stats=False)
+        step += 2
+        for (cb, Sb), (cr, Sr) in zip(bat, ref):
+            cb.sync()
+            cr.sync()
+            gb, gr = Sb.to_numpy(), Sr.to_numpy()
+            for k in ("q", "p", "eps", "rho", "f", "id"):
+                assert np.array_equal(gb[k], gr[k]), f"replay {rep}: {k} differs"
+            assert cb.observe(Sb)["E"] == cr.observe(Sr)["E"]
+for c, _ in ref + bat:
+    c.close()
+print("ok", flush=True)
+"""
+
+
+def test_batch_per_stream_graphs_match_eager_steps():
+    """With a hardware queue per stream the batch keeps one graph per stream;
+    the queue count is fixed when HIP starts, so this runs in a child process
+    (started, not exec'd, from this one) with GPU_MAX_HW_QUEUES = 8."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, GPU_MAX_HW_QUEUES="8")
+    say("batch per-stream graphs (child process)")
+    r = subprocess.run([sys.executable, "-c", _PER_STREAM_CHILD, root], env=env, cwd=root,
+                       capture_output=True, text=True, timeout=150)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout[-2000:] + r.stderr[-2000:]
