@@ -155,14 +155,14 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 // round partner x ^ s lies in the half).  Lane x of the segment is slot x of
 // cell A and of cell B.  Writes the task's particle list and its pairs in
 // round order with their levels.  `ok` = this segment has a task to do;
-// `intra` is the same for the whole wave (tasks of one pair never mix phase
-// 0 with the others, since ncell is even).
-template <int W>
+// INTRA (a phase-0 task) is the same for the whole wave (tasks of one pair
+// never mix phase 0 with the others, since ncell is even).
+template <int W, bool INTRA>
 __device__ __forceinline__ void schedule_segment(const DevParams &P, const TaskSpan &t, bool ok,
-                                                 bool intra,
                                                  const uint64_t *__restrict__ masks,
                                                  uint64_t *pairs, uint32_t *part_list)
 {
+    constexpr bool intra = INTRA;
     using M = typename std::conditional<W == 32, uint32_t, uint64_t>::type;
     const int lane = threadIdx.x & 63;
     const int base = lane & ~(W - 1), x = lane & (W - 1);
@@ -195,17 +195,18 @@ __device__ __forceinline__ void schedule_segment(const DevParams &P, const TaskS
         const int addr = (base + partner) << 2;   // byte address of the partner lane
         const bool act = (rm >> s) & 1u;
         const int la = __builtin_amdgcn_ds_bpermute(addr, LA);
-        const int lb = __builtin_amdgcn_ds_bpermute(addr, LB);
-        const bool actB_here = __builtin_amdgcn_ds_bpermute(addr, (int)act) != 0;
         const uint32_t pB = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)posB);
         bool own;
-        if (intra) {
+        if (INTRA) {   // one role per particle; the pair's two lanes agree on act
             own = act && x < partner;
-            if (act) LA = (LA > la ? LA : la) + 1;
-        } else {
+            LA = act ? max(LA, la) + 1 : LA;
+        } else {       // lane x is slot x of cell A and slot x of cell B
+            const int lb = __builtin_amdgcn_ds_bpermute(addr, LB);
+            const bool actB_here = __builtin_amdgcn_ds_bpermute(addr, (int)act) != 0;
             own = act;
-            if (act) LA = (LA > lb ? LA : lb) + 1;
-            if (actB_here) LB = (LB > la ? LB : la) + 1;
+            const int nLA = act ? max(LA, lb) + 1 : LA;
+            LB = actB_here ? max(LB, la) + 1 : LB;
+            LA = nLA;
         }
         const uint64_t bal = __ballot(own);
         const uint32_t blo = (uint32_t)bal, bhi = (uint32_t)(bal >> 32);
@@ -262,10 +263,19 @@ __global__ __launch_bounds__(64 * SCHED_WAVES) void k_schedule(const DevParams *
         if (widest <= 32) {
             const bool hi = lane >= 32;
             const TaskSpan t = hi ? tb : ta;   // field-wise select
-            schedule_segment<32>(P, t, hi ? okb : oka, ta.tc.slot == 0, masks, pairs, part_list);
+            if (ta.tc.slot == 0)   // both tasks of the pair are of one kind
+                schedule_segment<32, true>(P, t, hi ? okb : oka, masks, pairs, part_list);
+            else
+                schedule_segment<32, false>(P, t, hi ? okb : oka, masks, pairs, part_list);
         } else {
-            if (oka) schedule_segment<64>(P, ta, true, ta.tc.slot == 0, masks, pairs, part_list);
-            if (okb) schedule_segment<64>(P, tb, true, tb.tc.slot == 0, masks, pairs, part_list);
+            if (oka) {
+                if (ta.tc.slot == 0) schedule_segment<64, true>(P, ta, true, masks, pairs, part_list);
+                else schedule_segment<64, false>(P, ta, true, masks, pairs, part_list);
+            }
+            if (okb) {
+                if (tb.tc.slot == 0) schedule_segment<64, true>(P, tb, true, masks, pairs, part_list);
+                else schedule_segment<64, false>(P, tb, true, masks, pairs, part_list);
+            }
         }
     }
 }
