@@ -150,7 +150,8 @@ static void free_ctx(sdpd_ctx *c)
                     c->perm, c->cell_sorted, c->tq, c->tp, c->teps, c->trho, c->tf, c->tid,
                     c->masks, c->counters, c->err, c->obs_partial, c->obs_out,
                     c->dparams, c->task_count, c->task_np, c->pair_off, c->part_off,
-                    c->part_list, c->pairs, c->draws, c->qr, c->pi_f, c->dstep, c->q4};
+                    c->part_list, c->pairs, c->draws, c->qr, c->pi_f, c->dstep, c->q4,
+                    c->sweep, c->epoch};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
@@ -175,6 +176,7 @@ static int take_error(sdpd_ctx *c)
         uint32_t z = 0;
         if (hipMemcpy(c->err, &z, sizeof z, hipMemcpyHostToDevice) != hipSuccess) return SDPD_EHIP;
     }
+    if (e & ERR_STALL) return SDPD_EHIP;   // a sweep range gave up waiting (not expected)
     if (e & ERR_IDS) return SDPD_EINVAL;
     if (e & ERR_CELLCAP) return SDPD_ECELLCAP;
     if (e & ERR_NONFINITE) return SDPD_ENONFINITE;
@@ -300,6 +302,7 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     rc = rc ? rc : dalloc(&c->part_off, (size_t)NMASK * nce + 1);
     rc = rc ? rc : dalloc(&c->pairs, (size_t)c->pair_cap);
     rc = rc ? rc : dalloc(&c->draws, (size_t)4 * c->pair_cap);
+    rc = rc ? rc : dalloc(&c->epoch, (size_t)c->ncell + 1);
     rc = rc ? rc : dalloc(&c->dstep, 1);
     rc = rc ? rc : dalloc(&c->part_list, (size_t)c->part_cap);
     if (!rc)
@@ -308,6 +311,7 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     if (!rc) rc = launch_fill_u32(c, c->err, 0u, 1);
     if (!rc) rc = launch_fill_u64(c, c->counters, 0ull, CNT_N);
     if (!rc) rc = check_hip(hipStreamSynchronize(c->stream));
+    if (!rc) rc = fd_prepare_sweep(c);
     if (rc) {
         free_ctx(c);
         return rc;
@@ -496,7 +500,7 @@ int sdpd_tune(sdpd_ctx *c, const sdpd_tuning *t)
     const int rc = fd_check_tuning(c, &u);
     if (rc) return rc;
     c->tuning = u;
-    return SDPD_OK;
+    return fd_prepare_sweep(c);
 }
 
 int sdpd_fd_schedule_size(sdpd_ctx *c, int64_t *pairs, int64_t *staged)

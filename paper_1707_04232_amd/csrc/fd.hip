@@ -37,10 +37,14 @@
 // order.  Every pair of phases whose order is exchanged touches disjoint
 // particles, so the result equals the sweep in key order bit for bit.  For
 // the 13 forward offsets this gives 26 launches of 4 phases each.
+#include <string.h>
+
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "fd_math.hpp"
+#include "tasks.hpp"
 
 namespace sdpd {
 
@@ -96,21 +100,59 @@ __device__ __forceinline__ void fd_gather(const uint32_t *s_sorted, const uint32
     g.U = d23.y;
 }
 
-// FAST: the common case (EMS, Lucy kernel, zeta = 0) fixed at compile time
-template <bool FAST>
-__global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ Pp, FdLaunch L,
-                                                 const double4 *__restrict__ qrho, double *p,
-                                                 double *eps, const uint32_t *__restrict__ id,
-                                                 const uint32_t *__restrict__ pair_off,
-                                                 const uint32_t *__restrict__ part_off,
-                                                 const uint64_t *__restrict__ pairs,
-                                                 const uint32_t *__restrict__ part_list,
-                                                 uint32_t pair_cap, uint32_t part_cap,
-                                                 const uint64_t *__restrict__ dstep, double dt,
-                                                 double *draws,
-                                                 unsigned long long *counters, uint32_t *err)
+// Momenta and energies are the state that workgroups hand on to each other.
+// COHERENT: another workgroup of the same kernel, on any XCD, may have
+// written them, so they are read and written with agent-scope atomic loads
+// and stores (coherent across the XCDs' L2 caches); otherwise plain.
+template <bool COHERENT>
+__device__ __forceinline__ double state_load(const double *ptr)
 {
-    extern __shared__ __align__(16) unsigned char lds[];
+    if (COHERENT) return __hip_atomic_load(ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *ptr;
+}
+
+template <bool COHERENT>
+__device__ __forceinline__ void state_store(double *ptr, double v)
+{
+    if (COHERENT) __hip_atomic_store(ptr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *ptr = v;
+}
+
+// Arguments every range of the sweep reads or writes.
+struct FdArgs {
+    const double4 *qrho;
+    double *p, *eps;
+    const uint32_t *id, *pair_off, *part_off;
+    const uint64_t *pairs;
+    const uint32_t *part_list;
+    uint32_t pair_cap, part_cap;
+    const uint64_t *dstep;
+    double dt;
+    double *draws;
+    uint32_t *err;
+};
+
+// One task range: workgroup-range index b of the launch L (a range of
+// consecutive tasks of one of its phases), staged, sorted, drawn and applied
+// level by level.  FAST: the common case (EMS, Lucy kernel, zeta = 0) fixed
+// at compile time.
+template <bool FAST, bool COHERENT>
+__device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, int64_t b,
+                                         unsigned char *lds, const FdArgs &A, FdCount &cnt,
+                                         bool &negeps)
+{
+    const double4 *__restrict__ qrho = A.qrho;
+    double *p = A.p, *eps = A.eps;
+    const uint32_t *__restrict__ id = A.id;
+    const uint32_t *__restrict__ pair_off = A.pair_off;
+    const uint32_t *__restrict__ part_off = A.part_off;
+    const uint64_t *__restrict__ pairs = A.pairs;
+    const uint32_t *__restrict__ part_list = A.part_list;
+    const uint32_t pair_cap = A.pair_cap, part_cap = A.part_cap;
+    const uint64_t *__restrict__ dstep = A.dstep;
+    const double dt = A.dt;
+    double *draws = A.draws;
+    uint32_t *err = A.err;
     const int CP = L.cap_p, CE = L.cap_e;
     double *s_p = (double *)lds;
     double *s_eps = s_p + 3 * CP;
@@ -124,11 +166,9 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
     int *s_maxlv = (int *)(s_poff + (FD_MAXTASKS + 1));
     int *s_ntot = s_maxlv + 1;                        // sorted entries of the window
 
-    const DevParams &P = *Pp;
     const int lane = threadIdx.x;
     const int64_t n = P.n;
-    // phase of this workgroup and its task range
-    int64_t b = blockIdx.x;
+    // phase of this range and its tasks
     int k_ph = 0;
     while (k_ph + 1 < L.nph && b >= L.wg_end[k_ph]) ++k_ph;
     if (k_ph > 0) b -= L.wg_end[k_ph - 1];
@@ -136,8 +176,6 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
     const int64_t t0 = b * tpw;
     const int R = (int)(t0 + tpw < ntasks ? tpw : ntasks - t0);
     const int64_t T0 = task_base + t0;
-    FdCount cnt = {0u, 0u, 0u, 0u, 0u};
-    bool negeps = false;
 
     // offsets of the range's tasks (R + 1 values) and of the phase
     if (lane < R) {
@@ -189,10 +227,10 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
                 if (l < np) {
                     const int64_t g = gl[r];
                     s_gidx[l] = (uint32_t)g;
-                    s_p[l] = p[g];
-                    s_p[CP + l] = p[n + g];
-                    s_p[2 * CP + l] = p[2 * n + g];
-                    s_eps[l] = eps[g];
+                    s_p[l] = state_load<COHERENT>(p + g);
+                    s_p[CP + l] = state_load<COHERENT>(p + n + g);
+                    s_p[2 * CP + l] = state_load<COHERENT>(p + 2 * n + g);
+                    s_eps[l] = state_load<COHERENT>(eps + g);
                 }
             }
         }
@@ -376,14 +414,20 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
         // ---- write back momenta and energies
         for (int l = lane; l < np; l += 64) {
             const int64_t g = s_gidx[l];
-            p[g] = s_p[l];
-            p[n + g] = s_p[CP + l];
-            p[2 * n + g] = s_p[2 * CP + l];
-            eps[g] = s_eps[l];
+            state_store<COHERENT>(p + g, s_p[l]);
+            state_store<COHERENT>(p + n + g, s_p[CP + l]);
+            state_store<COHERENT>(p + 2 * n + g, s_p[2 * CP + l]);
+            state_store<COHERENT>(eps + g, s_eps[l]);
         }
         __syncthreads();
     }
-    // ---- counters: one atomic per counter per workgroup
+}
+
+// counters of a workgroup: one atomic per counter
+__device__ __forceinline__ void fd_flush_counters(const FdCount &cnt, bool negeps,
+                                                  unsigned long long *counters, uint32_t *err)
+{
+    const int lane = threadIdx.x;
     const uint32_t v0 = wave_sum_u32(cnt.proposed), v1 = wave_sum_u32(cnt.rej_energy);
     const uint32_t v2 = wave_sum_u32(cnt.rej_ratio), v3 = wave_sum_u32(cnt.marginal);
     const uint32_t v4 = wave_sum_u32(cnt.negeps);
@@ -396,6 +440,107 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
         if (v4) atomicAdd(&counters[CNT_NEGEPS], (unsigned long long)v4);
         if (any_neg) atomicOr(err, ERR_NEGEPS);
     }
+}
+
+// one launch: workgroup b = blockIdx.x applies range b of L
+template <bool FAST>
+__global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ Pp, FdLaunch L,
+                                                 FdArgs A, unsigned long long *counters)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    FdCount cnt = {0u, 0u, 0u, 0u, 0u};
+    bool negeps = false;
+    fd_range<FAST, false>(*Pp, L, (int64_t)blockIdx.x, lds, A, cnt, negeps);
+    fd_flush_counters(cnt, negeps, counters, A.err);
+}
+
+// The whole sweep in one launch.  Its ranges, in sweep order (group 0 =
+// phase 0, then the groups of mutually disjoint phases), are handed out by
+// an atomic counter, so a range is only taken by a running workgroup and
+// every range it waits for was taken before it.  Every group touches every
+// cell exactly once, so epoch[c] = the number of groups done on cell c: a
+// range of group g waits until its cells have epoch g, and sets them to
+// g + 1 once its momenta and energies are written (stores completed first).
+// The wait is bounded: past kSpinLimit polls it reports ERR_STALL and goes
+// on, so every workgroup ends.
+constexpr int FD_MAXGROUPS = 32;
+struct FdSweep {
+    int ngroups;
+    uint32_t nitems;
+    uint32_t group_end[FD_MAXGROUPS];   // cumulative ranges per group
+    FdLaunch launch[FD_MAXGROUPS];
+};
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+template <bool FAST>
+__global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ Pp,
+                                                 const FdSweep *__restrict__ SW, FdArgs A,
+                                                 uint32_t *work, uint32_t *epoch,
+                                                 unsigned long long *counters)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    const DevParams &P = *Pp;
+    const int lane = threadIdx.x;
+    FdCount cnt = {0u, 0u, 0u, 0u, 0u};
+    bool negeps = false;
+    const uint32_t nitems = SW->nitems;
+    for (;;) {
+        uint32_t it = 0u;
+        if (lane == 0) it = atomicAdd(work, 1u);
+        it = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)it, 0));
+        if (it >= nitems) break;
+        int g = 0;
+        while (it >= SW->group_end[g]) ++g;
+        const FdLaunch &L = SW->launch[g];
+        const int64_t b = (int64_t)it - (g > 0 ? (int64_t)SW->group_end[g - 1] : 0);
+        // the range's tasks (as fd_range finds them)
+        int k_ph = 0;
+        while (k_ph + 1 < L.nph && b >= L.wg_end[k_ph]) ++k_ph;
+        const int64_t bl = k_ph > 0 ? b - L.wg_end[k_ph - 1] : b;
+        const int64_t tpw = L.tpw[k_ph], ntasks = L.ntasks[k_ph];
+        const int64_t t0 = bl * tpw;
+        const int R = (int)(t0 + tpw < ntasks ? tpw : ntasks - t0);
+        const int64_t T0 = L.task_base[k_ph] + t0;
+        int64_t cA = -1, cB = -1;
+        if (lane < R) {
+            const TaskCells tc = task_cells(P, T0 + lane);
+            cA = tc.A;
+            cB = tc.slot == 0 ? -1 : tc.B;
+        }
+        if (g > 0) {
+            bool ready = lane >= R;
+            for (uint32_t spin = 0;; ++spin) {
+                if (!ready) {
+                    const uint32_t ea =
+                        __hip_atomic_load(epoch + cA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t eb = cB < 0 ? (uint32_t)g
+                                               : __hip_atomic_load(epoch + cB, __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    ready = ea >= (uint32_t)g && eb >= (uint32_t)g;
+                }
+                if (__ballot(!ready) == 0ull) break;
+                if (spin >= kSpinLimit) {
+                    if (lane == 0) atomicOr(A.err, ERR_STALL);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        // no memory access of the range moves above the wait (its state
+        // loads are themselves coherent, so no cache invalidation is needed)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        fd_range<FAST, true>(P, L, b, lds, A, cnt, negeps);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_s_waitcnt(0);   // the state stores have completed
+        if (lane < R) {
+            __hip_atomic_store(epoch + cA, (uint32_t)g + 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            if (cB >= 0)
+                __hip_atomic_store(epoch + cB, (uint32_t)g + 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    fd_flush_counters(cnt, negeps, counters, A.err);
 }
 
 // ---------------------------------------------------------------- host side
@@ -477,6 +622,12 @@ void fd_default_tuning(sdpd_ctx *c)
                                 c->max_lds) != hipSuccess ||
             hipFuncSetAttribute((const void *)k_fd_phase<true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                c->max_lds) != hipSuccess ||
+            hipFuncSetAttribute((const void *)k_fd_sweep<false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                c->max_lds) != hipSuccess ||
+            hipFuncSetAttribute((const void *)k_fd_sweep<true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                 c->max_lds) != hipSuccess) {
             (void)hipGetLastError();
             c->max_lds = 65536;
@@ -496,11 +647,41 @@ int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t)
     return SDPD_OK;
 }
 
-// one launch over the tasks of up to FD_MAXPH mutually disjoint phases
-static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, int nph,
-                         double dt_fd)
+// the launches of a sweep: phase 0, then each phase gets the level 1 + the
+// largest level of the earlier phases whose parity sets intersect its own,
+// and the phases of one level run together (at most FD_MAXPH per launch)
+static std::vector<std::vector<int>> fd_groups()
 {
-    FdLaunch L;
+    std::vector<std::vector<int>> groups(1, std::vector<int>(1, 0));
+    int lvl[105];
+    unsigned set[105];
+    int maxl = 0;
+    for (int p = 1; p <= 104; ++p) {
+        set[p] = phase_geom(p).parity_set;
+        lvl[p] = 1;
+        for (int r = 1; r < p; ++r)
+            if ((set[r] & set[p]) && lvl[r] + 1 > lvl[p]) lvl[p] = lvl[r] + 1;
+        maxl = std::max(maxl, lvl[p]);
+    }
+    for (int l = 1; l <= maxl; ++l) {
+        std::vector<int> g;
+        for (int p = 1; p <= 104; ++p) {
+            if (lvl[p] != l) continue;
+            g.push_back(p);
+            if ((int)g.size() == FD_MAXPH) {
+                groups.push_back(g);
+                g.clear();
+            }
+        }
+        if (!g.empty()) groups.push_back(g);
+    }
+    return groups;
+}
+
+// workgroup ranges of one launch over the tasks of up to FD_MAXPH mutually
+// disjoint phases; returns the number of ranges
+static int64_t fd_launch_geometry(const sdpd_ctx *c, const int *phases, int nph, FdLaunch &L)
+{
     L.nph = nph;
     L.cap_p = 0;
     L.cap_e = 0;
@@ -520,21 +701,99 @@ static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, in
         L.cap_p = std::max(L.cap_p, (int)c->tuning.fd_lds_particles[cls]);
         L.cap_e = std::max(L.cap_e, (int)c->tuning.fd_lds_pairs[cls]);
     }
+    return wg;
+}
+
+static bool fd_fast(const sdpd_ctx *c)
+{
+    return c->dp.fd == SDPD_FD_EMS && c->dp.kernel == SDPD_KERNEL_LUCY && c->dp.par_twice_perp;
+}
+
+static FdArgs fd_args(const sdpd_ctx *c, const sdpd_state *s, double dt_fd)
+{
+    FdArgs A;
+    A.qrho = reinterpret_cast<const double4 *>(c->q4);
+    A.p = s->p;
+    A.eps = s->eps;
+    A.id = s->id;
+    A.pair_off = c->pair_off;
+    A.part_off = c->part_off;
+    A.pairs = c->pairs;
+    A.part_list = c->part_list;
+    A.pair_cap = (uint32_t)c->pair_cap;
+    A.part_cap = (uint32_t)c->part_cap;
+    A.dstep = c->dstep;
+    A.dt = dt_fd;
+    A.draws = c->draws;
+    A.err = c->err;
+    return A;
+}
+
+// one launch per group (the sweep kernel's fallback)
+static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, int nph,
+                         double dt_fd)
+{
+    FdLaunch L;
+    const int64_t wg = fd_launch_geometry(c, phases, nph, L);
     if (wg == 0) return SDPD_OK;
     if (wg > 0x7fffffffLL) return SDPD_EINVAL;
     const size_t lds = fd_lds_bytes(L.cap_p, L.cap_e);
     if (lds > (size_t)c->max_lds) return SDPD_EINVAL;
     timer_begin(c, TK_FD);
-    const bool fast = c->dp.fd == SDPD_FD_EMS && c->dp.kernel == SDPD_KERNEL_LUCY &&
-                      c->dp.par_twice_perp;
-    auto kern = fast ? k_fd_phase<true> : k_fd_phase<false>;
+    auto kern = fd_fast(c) ? k_fd_phase<true> : k_fd_phase<false>;
     hipLaunchKernelGGL(kern, dim3((unsigned)wg), dim3(64), lds, c->stream, c->dparams, L,
-                       reinterpret_cast<const double4 *>(c->q4), s->p, s->eps, s->id,
-                       c->pair_off, c->part_off, c->pairs,
-                       c->part_list, (uint32_t)c->pair_cap, (uint32_t)c->part_cap,
-                       c->dstep, dt_fd, c->draws, c->counters, c->err);
+                       fd_args(c, s, dt_fd), c->counters);
     timer_end(c, TK_FD);
     return check_hip(hipGetLastError());
+}
+
+// Table of the sweep kernel (ranges of every group, in sweep order) and its
+// launch size, rebuilt whenever the tuning changes.  The sweep kernel needs
+// every group to touch every cell exactly once (its phases' parity sets
+// partition the 8 parities); otherwise the per-group launches are used.
+int fd_prepare_sweep(sdpd_ctx *c)
+{
+    c->sweep_ok = 0;
+    const std::vector<std::vector<int>> groups = fd_groups();
+    if ((int)groups.size() > FD_MAXGROUPS) return SDPD_OK;
+    FdSweep h;
+    memset(&h, 0, sizeof h);
+    h.ngroups = (int)groups.size();
+    int64_t total = 0;
+    size_t lds = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        unsigned cover = 0;
+        for (int ph : groups[g]) {
+            const unsigned ps = phase_geom(ph).parity_set;
+            if (cover & ps) return SDPD_OK;
+            cover |= ps;
+        }
+        if (cover != 0xFFu) return SDPD_OK;
+        total += fd_launch_geometry(c, groups[g].data(), (int)groups[g].size(), h.launch[g]);
+        if (total > 0x7fffffffLL) return SDPD_OK;
+        h.group_end[g] = (uint32_t)total;
+        lds = std::max(lds, fd_lds_bytes(h.launch[g].cap_p, h.launch[g].cap_e));
+    }
+    h.nitems = (uint32_t)total;
+    if (lds > (size_t)c->max_lds) return SDPD_OK;
+    if (!c->sweep && hipMalloc(&c->sweep, sizeof(FdSweep)) != hipSuccess) {
+        c->sweep = nullptr;
+        return SDPD_ENOMEM;
+    }
+    int rc = check_hip(hipMemcpy(c->sweep, &h, sizeof h, hipMemcpyHostToDevice));
+    if (rc) return rc;
+    int per_cu = 0, cus = 0;
+    const void *kern = fd_fast(c) ? (const void *)k_fd_sweep<true> : (const void *)k_fd_sweep<false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess || per_cu < 1 || cus < 1) {
+        (void)hipGetLastError();
+        return SDPD_OK;
+    }
+    c->sweep_lds = lds;
+    c->sweep_grid = (int)std::min<int64_t>((int64_t)per_cu * cus, std::max<int64_t>(total, 1));
+    c->sweep_ok = 1;
+    return SDPD_OK;
 }
 
 // (x, y, z, rho) record of every particle for the pair gathers of the sweep
@@ -564,31 +823,19 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
     timer_end(c, TK_SCHED);
     if ((rc = check_hip(hipGetLastError()))) return rc;
     c->fd_swept = 1;
-    const int zero = 0;
-    if ((rc = launch_phases(c, s, &zero, 1, dt_fd))) return rc;
-    // levels of the inter-cell phases (phase 0 touches every cell and runs first)
-    int lvl[105];
-    unsigned set[105];
-    int maxl = 0;
-    for (int p = 1; p <= 104; ++p) {
-        set[p] = phase_geom(p).parity_set;
-        lvl[p] = 1;
-        for (int r = 1; r < p; ++r)
-            if ((set[r] & set[p]) && lvl[r] + 1 > lvl[p]) lvl[p] = lvl[r] + 1;
-        maxl = std::max(maxl, lvl[p]);
+    if (c->sweep_ok) {
+        // epochs of the cells and the range counter start at zero
+        if ((rc = launch_fill_u32(c, c->epoch, 0u, c->ncell + 1))) return rc;
+        timer_begin(c, TK_FD);
+        auto kern = fd_fast(c) ? k_fd_sweep<true> : k_fd_sweep<false>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)c->sweep_grid), dim3(64), c->sweep_lds, c->stream,
+                           c->dparams, (const FdSweep *)c->sweep, fd_args(c, s, dt_fd),
+                           c->epoch + c->ncell, c->epoch, c->counters);
+        timer_end(c, TK_FD);
+        return check_hip(hipGetLastError());
     }
-    for (int l = 1; l <= maxl; ++l) {
-        int group[FD_MAXPH], ng = 0;
-        for (int p = 1; p <= 104; ++p) {
-            if (lvl[p] != l) continue;
-            group[ng++] = p;
-            if (ng == FD_MAXPH) {
-                if ((rc = launch_phases(c, s, group, ng, dt_fd))) return rc;
-                ng = 0;
-            }
-        }
-        if (ng && (rc = launch_phases(c, s, group, ng, dt_fd))) return rc;
-    }
+    for (const std::vector<int> &g : fd_groups())
+        if ((rc = launch_phases(c, s, g.data(), (int)g.size(), dt_fd))) return rc;
     return SDPD_OK;
 }
 

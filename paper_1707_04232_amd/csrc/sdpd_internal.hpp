@@ -13,7 +13,8 @@ namespace sdpd {
 
 // sticky device error bits
 enum : uint32_t {
-    ERR_CELLCAP = 1u, ERR_NEGEPS = 2u, ERR_NONFINITE = 4u, ERR_PAIRCAP = 8u, ERR_IDS = 16u
+    ERR_CELLCAP = 1u, ERR_NEGEPS = 2u, ERR_NONFINITE = 4u, ERR_PAIRCAP = 8u, ERR_IDS = 16u,
+    ERR_STALL = 32u
 };
 struct AdjointWork;   // adjoint.hip
 
@@ -105,6 +106,10 @@ struct sdpd_ctx {
     uint32_t *task_count, *task_np, *pair_off, *part_off, *part_list;
     uint64_t *pairs;
     double *draws;               // 4 per pair entry: the sweep's random draws in sorted order
+    void *sweep = nullptr;       // device table of the sweep kernel (fd.hip)
+    size_t sweep_lds = 0;
+    int sweep_grid = 0, sweep_ok = 0;
+    uint32_t *epoch = nullptr;   // ncell + 1: per-cell group epochs, then the range counter
     uint64_t *dstep;             // step index of the draws, on the device
     sdpd::AdjointWork *adj;      // checkpoints and cotangents of the adjoint (lazily)
     int64_t pair_cap, part_cap;
@@ -134,6 +139,7 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd);
 int enqueue_step(sdpd_ctx *c, const sdpd_state *s, uint64_t step, bool set_step);
 void fd_default_tuning(sdpd_ctx *c);
 int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t);
+int fd_prepare_sweep(sdpd_ctx *c);   // after any change of the tuning
 int run_observe(sdpd_ctx *c, const sdpd_state *s, double *dst_record);
 void adjoint_free(AdjointWork *a);
 
