@@ -36,8 +36,9 @@ FLOPS_PER_EMS_PAIR = 773.0
 # pair its schedule entry (8)
 BYTES_PER_STAGED = 104.0
 BYTES_PER_PAIR_ENTRY = 8.0
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "fd_phase_traffic.json")
-FD_SOURCES = ["fd.hip", "fd_math.hpp", "fd_elem.hpp", "schedule.hip", "sdpd_internal.hpp"]
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "fd_sweep_traffic.json")
+FD_SOURCES = ["fd.hip", "fd_math.hpp", "fd_elem.hpp", "tasks.hpp", "schedule.hip",
+              "sdpd_internal.hpp", "fastdiv.hpp"]
 
 
 def fd_source_hash():
@@ -330,7 +331,7 @@ def main():
         launches_per_sweep = fd_launches / max(nsweeps, 1)
         alg_bytes = (last_staged * BYTES_PER_STAGED + last_pairs * BYTES_PER_PAIR_ENTRY) \
             / launches_per_sweep
-        roof = {"bound": "alu", "kernel": "k_fd_phase", "achieved": achieved,
+        roof = {"bound": "alu", "kernel": "k_fd_sweep", "achieved": achieved,
                 "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": measured_traffic(),
                 "algorithmic_bytes_per_launch": alg_bytes,

@@ -22,21 +22,26 @@
 // not change during the sweep: positions and densities are packed once per
 // sweep into one (x, y, z, rho) record per particle and read from global
 // memory two level steps ahead of their use, which keeps the LDS footprint
-// at 36 B per particle and leaves room for more resident waves.  The random draws of a
-// pair depend only on (step, ids): after the level sort they are computed for
-// all of the batch's pairs at full lane occupancy (which also orients every
-// pair, i = smaller id) and stored in sorted order in a global buffer, from
-// which the level steps prefetch them with the positions.
+// at 36 B per particle and leaves room for more resident waves.  The random
+// draws of a pair depend only on (step, ids): after the level sort they are
+// computed for all of the batch's pairs at full lane occupancy (which also
+// orients every pair, i = smaller id) and stored in sorted order in a global
+// buffer, from which the level steps prefetch them with the positions.
 //
 // Phases that touch disjoint cells commute.  Phase 1 + 8 o + pi touches the
 // cells of parity pi (as A) and pi ^ b_o (as B = A + delta_o, b_o the parity
 // bits that delta_o flips; the number of cells per axis is even, so this
 // holds across the periodic boundary).  Each phase is given the level
 // 1 + the largest level of the earlier phases whose parity sets intersect
-// its own; the phases of one level run in one launch, levels in ascending
-// order.  Every pair of phases whose order is exchanged touches disjoint
-// particles, so the result equals the sweep in key order bit for bit.  For
-// the 13 forward offsets this gives 26 launches of 4 phases each.
+// its own; the phases of one level form a group.  For the 13 forward offsets
+// this gives 26 groups of 4 phases, each touching every cell exactly once;
+// with phase 0, 27 groups.  The whole sweep is one persistent launch: the
+// task ranges of all groups, in group order, are handed out by an atomic
+// counter, and a range of group g waits only until every cell it touches
+// has been released by group g - 1 (per-cell epochs), so the groups overlap
+// instead of draining one launch before the next.  Every pair of phases
+// whose order is exchanged touches disjoint particles, so the result equals
+// the sweep in key order bit for bit.
 #include <string.h>
 
 #include <algorithm>
@@ -100,22 +105,18 @@ __device__ __forceinline__ void fd_gather(const uint32_t *s_sorted, const uint32
     g.U = d23.y;
 }
 
-// Momenta and energies are the state that workgroups hand on to each other.
-// COHERENT: another workgroup of the same kernel, on any XCD, may have
-// written them, so they are read and written with agent-scope atomic loads
-// and stores (coherent across the XCDs' L2 caches); otherwise plain.
-template <bool COHERENT>
+// Momenta and energies are the state that workgroups hand on to each other:
+// another workgroup of the same kernel, on any XCD, may have written them,
+// so they are read and written with agent-scope atomic loads and stores
+// (coherent across the XCDs' L2 caches, with no cache flush).
 __device__ __forceinline__ double state_load(const double *ptr)
 {
-    if (COHERENT) return __hip_atomic_load(ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return *ptr;
+    return __hip_atomic_load(ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <bool COHERENT>
 __device__ __forceinline__ void state_store(double *ptr, double v)
 {
-    if (COHERENT) __hip_atomic_store(ptr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else *ptr = v;
+    __hip_atomic_store(ptr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Arguments every range of the sweep reads or writes.
@@ -136,7 +137,7 @@ struct FdArgs {
 // consecutive tasks of one of its phases), staged, sorted, drawn and applied
 // level by level.  FAST: the common case (EMS, Lucy kernel, zeta = 0) fixed
 // at compile time.
-template <bool FAST, bool COHERENT>
+template <bool FAST>
 __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, int64_t b,
                                          unsigned char *lds, const FdArgs &A, FdCount &cnt,
                                          bool &negeps)
@@ -227,10 +228,10 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
                 if (l < np) {
                     const int64_t g = gl[r];
                     s_gidx[l] = (uint32_t)g;
-                    s_p[l] = state_load<COHERENT>(p + g);
-                    s_p[CP + l] = state_load<COHERENT>(p + n + g);
-                    s_p[2 * CP + l] = state_load<COHERENT>(p + 2 * n + g);
-                    s_eps[l] = state_load<COHERENT>(eps + g);
+                    s_p[l] = state_load(p + g);
+                    s_p[CP + l] = state_load(p + n + g);
+                    s_p[2 * CP + l] = state_load(p + 2 * n + g);
+                    s_eps[l] = state_load(eps + g);
                 }
             }
         }
@@ -414,10 +415,10 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
         // ---- write back momenta and energies
         for (int l = lane; l < np; l += 64) {
             const int64_t g = s_gidx[l];
-            state_store<COHERENT>(p + g, s_p[l]);
-            state_store<COHERENT>(p + n + g, s_p[CP + l]);
-            state_store<COHERENT>(p + 2 * n + g, s_p[2 * CP + l]);
-            state_store<COHERENT>(eps + g, s_eps[l]);
+            state_store(p + g, s_p[l]);
+            state_store(p + n + g, s_p[CP + l]);
+            state_store(p + 2 * n + g, s_p[2 * CP + l]);
+            state_store(eps + g, s_eps[l]);
         }
         __syncthreads();
     }
@@ -440,18 +441,6 @@ __device__ __forceinline__ void fd_flush_counters(const FdCount &cnt, bool negep
         if (v4) atomicAdd(&counters[CNT_NEGEPS], (unsigned long long)v4);
         if (any_neg) atomicOr(err, ERR_NEGEPS);
     }
-}
-
-// one launch: workgroup b = blockIdx.x applies range b of L
-template <bool FAST>
-__global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ Pp, FdLaunch L,
-                                                 FdArgs A, unsigned long long *counters)
-{
-    extern __shared__ __align__(16) unsigned char lds[];
-    FdCount cnt = {0u, 0u, 0u, 0u, 0u};
-    bool negeps = false;
-    fd_range<FAST, false>(*Pp, L, (int64_t)blockIdx.x, lds, A, cnt, negeps);
-    fd_flush_counters(cnt, negeps, counters, A.err);
 }
 
 // The whole sweep in one launch.  Its ranges, in sweep order (group 0 =
@@ -529,7 +518,7 @@ __global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ P
         // no memory access of the range moves above the wait (its state
         // loads are themselves coherent, so no cache invalidation is needed)
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        fd_range<FAST, true>(P, L, b, lds, A, cnt, negeps);
+        fd_range<FAST>(P, L, b, lds, A, cnt, negeps);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_s_waitcnt(0);   // the state stores have completed
         if (lane < R) {
@@ -617,13 +606,7 @@ void fd_default_tuning(sdpd_ctx *c)
     }
     if (c->max_lds > 65536) {
         // allow dynamic LDS beyond 64 KiB where the device has it
-        if (hipFuncSetAttribute((const void *)k_fd_phase<false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                c->max_lds) != hipSuccess ||
-            hipFuncSetAttribute((const void *)k_fd_phase<true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                c->max_lds) != hipSuccess ||
-            hipFuncSetAttribute((const void *)k_fd_sweep<false>,
+        if (hipFuncSetAttribute((const void *)k_fd_sweep<false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 c->max_lds) != hipSuccess ||
             hipFuncSetAttribute((const void *)k_fd_sweep<true>,
@@ -729,33 +712,15 @@ static FdArgs fd_args(const sdpd_ctx *c, const sdpd_state *s, double dt_fd)
     return A;
 }
 
-// one launch per group (the sweep kernel's fallback)
-static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, int nph,
-                         double dt_fd)
-{
-    FdLaunch L;
-    const int64_t wg = fd_launch_geometry(c, phases, nph, L);
-    if (wg == 0) return SDPD_OK;
-    if (wg > 0x7fffffffLL) return SDPD_EINVAL;
-    const size_t lds = fd_lds_bytes(L.cap_p, L.cap_e);
-    if (lds > (size_t)c->max_lds) return SDPD_EINVAL;
-    timer_begin(c, TK_FD);
-    auto kern = fd_fast(c) ? k_fd_phase<true> : k_fd_phase<false>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)wg), dim3(64), lds, c->stream, c->dparams, L,
-                       fd_args(c, s, dt_fd), c->counters);
-    timer_end(c, TK_FD);
-    return check_hip(hipGetLastError());
-}
-
 // Table of the sweep kernel (ranges of every group, in sweep order) and its
-// launch size, rebuilt whenever the tuning changes.  The sweep kernel needs
-// every group to touch every cell exactly once (its phases' parity sets
-// partition the 8 parities); otherwise the per-group launches are used.
+// launch size, rebuilt whenever the tuning changes.  The epochs need every
+// group to touch every cell exactly once: its phases' parity sets partition
+// the 8 parities (true of the 26 groups of the 13 forward offsets; checked).
 int fd_prepare_sweep(sdpd_ctx *c)
 {
     c->sweep_ok = 0;
     const std::vector<std::vector<int>> groups = fd_groups();
-    if ((int)groups.size() > FD_MAXGROUPS) return SDPD_OK;
+    if ((int)groups.size() > FD_MAXGROUPS) return SDPD_EINVAL;
     FdSweep h;
     memset(&h, 0, sizeof h);
     h.ngroups = (int)groups.size();
@@ -765,17 +730,17 @@ int fd_prepare_sweep(sdpd_ctx *c)
         unsigned cover = 0;
         for (int ph : groups[g]) {
             const unsigned ps = phase_geom(ph).parity_set;
-            if (cover & ps) return SDPD_OK;
+            if (cover & ps) return SDPD_EINVAL;
             cover |= ps;
         }
-        if (cover != 0xFFu) return SDPD_OK;
+        if (cover != 0xFFu) return SDPD_EINVAL;
         total += fd_launch_geometry(c, groups[g].data(), (int)groups[g].size(), h.launch[g]);
-        if (total > 0x7fffffffLL) return SDPD_OK;
+        if (total > 0x7fffffffLL) return SDPD_EINVAL;
         h.group_end[g] = (uint32_t)total;
         lds = std::max(lds, fd_lds_bytes(h.launch[g].cap_p, h.launch[g].cap_e));
     }
     h.nitems = (uint32_t)total;
-    if (lds > (size_t)c->max_lds) return SDPD_OK;
+    if (lds > (size_t)c->max_lds) return SDPD_EINVAL;
     if (!c->sweep && hipMalloc(&c->sweep, sizeof(FdSweep)) != hipSuccess) {
         c->sweep = nullptr;
         return SDPD_ENOMEM;
@@ -788,7 +753,7 @@ int fd_prepare_sweep(sdpd_ctx *c)
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
             hipSuccess || per_cu < 1 || cus < 1) {
         (void)hipGetLastError();
-        return SDPD_OK;
+        return SDPD_EHIP;
     }
     c->sweep_lds = lds;
     c->sweep_grid = (int)std::min<int64_t>((int64_t)per_cu * cus, std::max<int64_t>(total, 1));
@@ -823,19 +788,16 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
     timer_end(c, TK_SCHED);
     if ((rc = check_hip(hipGetLastError()))) return rc;
     c->fd_swept = 1;
-    if (c->sweep_ok) {
-        // epochs of the cells and the range counter start at zero
-        if ((rc = launch_fill_u32(c, c->epoch, 0u, c->ncell + 1))) return rc;
-        timer_begin(c, TK_FD);
-        auto kern = fd_fast(c) ? k_fd_sweep<true> : k_fd_sweep<false>;
-        hipLaunchKernelGGL(kern, dim3((unsigned)c->sweep_grid), dim3(64), c->sweep_lds, c->stream,
-                           c->dparams, (const FdSweep *)c->sweep, fd_args(c, s, dt_fd),
-                           c->epoch + c->ncell, c->epoch, c->counters);
-        timer_end(c, TK_FD);
-        return check_hip(hipGetLastError());
-    }
-    for (const std::vector<int> &g : fd_groups())
-        if ((rc = launch_phases(c, s, g.data(), (int)g.size(), dt_fd))) return rc;
+    if (!c->sweep_ok) return SDPD_EINVAL;
+    // epochs of the cells and the range counter start at zero
+    if ((rc = launch_fill_u32(c, c->epoch, 0u, c->ncell + 1))) return rc;
+    timer_begin(c, TK_FD);
+    auto kern = fd_fast(c) ? k_fd_sweep<true> : k_fd_sweep<false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)c->sweep_grid), dim3(64), c->sweep_lds, c->stream,
+                       c->dparams, (const FdSweep *)c->sweep, fd_args(c, s, dt_fd),
+                       c->epoch + c->ncell, c->epoch, c->counters);
+    timer_end(c, TK_FD);
+    return check_hip(hipGetLastError());
     return SDPD_OK;
 }
 
