@@ -201,7 +201,8 @@ int sdpd_timing(sdpd_ctx *ctx, double ms[6], int64_t launches[6]);
  * A workgroup whose tasks need more than its capacity processes them in
  * several batches.  The LDS of one workgroup, 36 B per particle + 4 B per
  * pair entry + 1320 B, must fit the device's per-workgroup limit.  Fields
- * equal to 0 in sdpd_tune keep the current value; sdpd_get_tuning reports
+ * equal to 0 in sdpd_tune keep the current value (sdpd_tune waits for the
+ * context's stream first); sdpd_get_tuning reports
  * the values in use (the defaults scale with the mean particles per cell).
  * SDPD_EINVAL for out-of-range values; nothing is changed then.          */
 typedef struct {
@@ -225,7 +226,8 @@ int sdpd_get_tuning(sdpd_ctx *ctx, sdpd_tuning *out);
  * streams (environment GPU_MAX_HW_QUEUES, 4 when unset), else one graph
  * that forks to and joins the boxes' streams.  sdpd_batch_run
  * replays it for steps step0 .. step0+nsteps-1 (both multiples of
- * fd_every): every box advances exactly as with sdpd_step on its own (bit
+ * fd_every; SDPD_EINVAL if a context was retuned with sdpd_tune after the
+ * capture): every box advances exactly as with sdpd_step on its own (bit
  * for bit), the boxes of different streams concurrently.  It is
  * asynchronous: later work on a box's stream waits for it; sdpd_sync /
  * sdpd_observe on a context report errors and observables.  Steps follow

@@ -151,7 +151,7 @@ static void free_ctx(sdpd_ctx *c)
                     c->masks, c->counters, c->err, c->obs_partial, c->obs_out,
                     c->dparams, c->task_count, c->task_np, c->pair_off, c->part_off,
                     c->part_list, c->pairs, c->draws, c->qr, c->pi_f, c->dstep, c->q4,
-                    c->sweep, c->epoch};
+                    c->sweep, c->epoch, c->sweep_order};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
@@ -500,6 +500,7 @@ int sdpd_tune(sdpd_ctx *c, const sdpd_tuning *t)
     const int rc = fd_check_tuning(c, &u);
     if (rc) return rc;
     c->tuning = u;
+    ++c->tune_gen;   // graphs captured before keep the old launch size
     return fd_prepare_sweep(c);
 }
 

@@ -21,6 +21,7 @@
 struct sdpd_batch {
     std::vector<sdpd_ctx *> ctx;
     std::vector<sdpd_state> st;
+    std::vector<int> gen;               // the contexts' tuning at capture
     std::vector<hipStream_t> streams;   // distinct streams of the boxes
     std::vector<hipEvent_t> join, ready;
     hipStream_t origin = nullptr;
@@ -84,6 +85,7 @@ int sdpd_batch_create(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
     if (!b) return SDPD_ENOMEM;
     b->ctx.assign(ctxs, ctxs + nbox);
     b->st.assign(states, states + nbox);
+    for (sdpd_ctx *c : b->ctx) b->gen.push_back(c->tune_gen);
     b->theta = theta;
     for (sdpd_ctx *c : b->ctx)
         if (std::find(b->streams.begin(), b->streams.end(), c->stream) == b->streams.end())
@@ -171,6 +173,8 @@ int sdpd_batch_run(sdpd_batch *b, uint64_t step0, int nsteps)
 {
     if (!b || nsteps < 0 || step0 % (uint64_t)b->theta != 0 || nsteps % b->theta != 0)
         return SDPD_EINVAL;
+    for (size_t k = 0; k < b->ctx.size(); ++k)
+        if (b->ctx[k]->tune_gen != b->gen[k]) return SDPD_EINVAL;   // retuned since the capture
     if (nsteps == 0) return SDPD_OK;
     int rc;
     for (sdpd_ctx *c : b->ctx)

@@ -443,10 +443,11 @@ __device__ __forceinline__ void fd_flush_counters(const FdCount &cnt, bool negep
     }
 }
 
-// The whole sweep in one launch.  Its ranges, in sweep order (group 0 =
-// phase 0, then the groups of mutually disjoint phases), are handed out by
-// an atomic counter, so a range is only taken by a running workgroup and
-// every range it waits for was taken before it.  Every group touches every
+// The whole sweep in one launch.  Its ranges, group by group (group 0 =
+// phase 0, then the groups of mutually disjoint phases; inside a group in
+// the order of `order`), are handed out by an atomic counter, so a range is
+// only taken by a running workgroup and every range it waits for was taken
+// before it.  Every group touches every
 // cell exactly once, so epoch[c] = the number of groups done on cell c: a
 // range of group g waits until its cells have epoch g, and sets them to
 // g + 1 once its momenta and energies are written (stores completed first).
@@ -463,7 +464,8 @@ constexpr uint32_t kSpinLimit = 1u << 20;
 
 template <bool FAST>
 __global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ Pp,
-                                                 const FdSweep *__restrict__ SW, FdArgs A,
+                                                 const FdSweep *__restrict__ SW,
+                                                 const uint32_t *__restrict__ order, FdArgs A,
                                                  uint32_t *work, uint32_t *epoch,
                                                  unsigned long long *counters)
 {
@@ -481,7 +483,7 @@ __global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ P
         int g = 0;
         while (it >= SW->group_end[g]) ++g;
         const FdLaunch &L = SW->launch[g];
-        const int64_t b = (int64_t)it - (g > 0 ? (int64_t)SW->group_end[g - 1] : 0);
+        const int64_t b = order[it];   // range index within group g
         // the range's tasks (as fd_range finds them)
         int k_ph = 0;
         while (k_ph + 1 < L.nph && b >= L.wg_end[k_ph]) ++k_ph;
@@ -716,8 +718,80 @@ static FdArgs fd_args(const sdpd_ctx *c, const sdpd_state *s, double dt_fd)
 // launch size, rebuilt whenever the tuning changes.  The epochs need every
 // group to touch every cell exactly once: its phases' parity sets partition
 // the 8 parities (true of the 26 groups of the 13 forward offsets; checked).
+// cells of task T (the host form of task_cells); B = -1 for a phase-0 task
+static void task_cells_host(const sdpd_ctx *c, int64_t T, int64_t &A, int64_t &B)
+{
+    const int64_t ncell = c->ncell;
+    const int nx = c->dp.nc[0], ny = c->dp.nc[1], nz = c->dp.nc[2];
+    if (T < ncell) {
+        A = T;
+        B = -1;
+        return;
+    }
+    const int64_t per = ncell / 8, u = T - ncell;
+    const int p = 1 + (int)(u / per);
+    const int64_t t = u % per;
+    const int o = (p - 1) / 8, pi = (p - 1) % 8, k = 14 + o;
+    const int64_t hx = nx / 2, hy = ny / 2;
+    const int tx = (int)(t % hx), ty = (int)((t / hx) % hy), tz = (int)(t / (hx * hy));
+    const int ax = 2 * tx + (pi & 1), ay = 2 * ty + ((pi >> 1) & 1), az = 2 * tz + (pi >> 2);
+    const int bx = (ax + k % 3 - 1 + nx) % nx, by = (ay + (k / 3) % 3 - 1 + ny) % ny,
+              bz = (az + k / 9 - 1 + nz) % nz;
+    A = ax + (int64_t)nx * (ay + (int64_t)ny * az);
+    B = bx + (int64_t)nx * (by + (int64_t)ny * bz);
+}
+
+// Order of the ranges inside each group: by the latest position, in the
+// hand-out order, of the ranges of the previous group they wait for (ties in
+// task order), so that ranges whose cells are released first are taken first.
+static std::vector<uint32_t> fd_range_order(const sdpd_ctx *c, const FdSweep &h)
+{
+    std::vector<uint32_t> order(h.nitems);
+    std::vector<int64_t> last(c->ncell, -1);   // hand-out position of the range that last touched c
+    std::vector<std::pair<int64_t, uint32_t>> keyed;
+    std::vector<std::vector<int64_t>> cells;
+    uint32_t begin = 0;
+    for (int g = 0; g < h.ngroups; ++g) {
+        const FdLaunch &L = h.launch[g];
+        const uint32_t nb = h.group_end[g] - begin;
+        keyed.assign(nb, std::make_pair((int64_t)-1, 0u));
+        cells.assign(nb, std::vector<int64_t>());
+        for (uint32_t b = 0; b < nb; ++b) {
+            int k_ph = 0;
+            while (k_ph + 1 < L.nph && (int64_t)b >= L.wg_end[k_ph]) ++k_ph;
+            const int64_t bl = k_ph > 0 ? (int64_t)b - L.wg_end[k_ph - 1] : (int64_t)b;
+            const int64_t t0 = bl * L.tpw[k_ph];
+            const int64_t t1 = std::min(t0 + L.tpw[k_ph], L.ntasks[k_ph]);
+            int64_t key = -1;
+            for (int64_t t = t0; t < t1; ++t) {
+                int64_t A, B;
+                task_cells_host(c, L.task_base[k_ph] + t, A, B);
+                cells[b].push_back(A);
+                key = std::max(key, last[A]);
+                if (B >= 0) {
+                    cells[b].push_back(B);
+                    key = std::max(key, last[B]);
+                }
+            }
+            keyed[b] = std::make_pair(key, b);
+        }
+        std::stable_sort(keyed.begin(), keyed.end(),
+                         [](const std::pair<int64_t, uint32_t> &x,
+                            const std::pair<int64_t, uint32_t> &y) { return x.first < y.first; });
+        for (uint32_t r = 0; r < nb; ++r) {
+            const uint32_t b = keyed[r].second;
+            order[begin + r] = b;
+            for (int64_t cc : cells[b]) last[cc] = begin + r;
+        }
+        begin = h.group_end[g];
+    }
+    return order;
+}
+
 int fd_prepare_sweep(sdpd_ctx *c)
 {
+    // the table and the order are rewritten in place: no sweep may be running
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return SDPD_EHIP;
     c->sweep_ok = 0;
     const std::vector<std::vector<int>> groups = fd_groups();
     if ((int)groups.size() > FD_MAXGROUPS) return SDPD_EINVAL;
@@ -747,6 +821,19 @@ int fd_prepare_sweep(sdpd_ctx *c)
     }
     int rc = check_hip(hipMemcpy(c->sweep, &h, sizeof h, hipMemcpyHostToDevice));
     if (rc) return rc;
+    const std::vector<uint32_t> order = fd_range_order(c, h);
+    // one range per task at most: the buffer is sized once and never moves
+    const size_t order_cap = (size_t)NMASK * (size_t)c->ncell + 1;
+    if (order.size() > order_cap) return SDPD_EINVAL;
+    if (!c->sweep_order &&
+        hipMalloc((void **)&c->sweep_order, sizeof(uint32_t) * order_cap) != hipSuccess) {
+        c->sweep_order = nullptr;
+        return SDPD_ENOMEM;
+    }
+    if (!order.empty() &&
+        (rc = check_hip(hipMemcpy(c->sweep_order, order.data(), sizeof(uint32_t) * order.size(),
+                                  hipMemcpyHostToDevice))))
+        return rc;
     int per_cu = 0, cus = 0;
     const void *kern = fd_fast(c) ? (const void *)k_fd_sweep<true> : (const void *)k_fd_sweep<false>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds) != hipSuccess ||
@@ -794,7 +881,7 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
     timer_begin(c, TK_FD);
     auto kern = fd_fast(c) ? k_fd_sweep<true> : k_fd_sweep<false>;
     hipLaunchKernelGGL(kern, dim3((unsigned)c->sweep_grid), dim3(64), c->sweep_lds, c->stream,
-                       c->dparams, (const FdSweep *)c->sweep, fd_args(c, s, dt_fd),
+                       c->dparams, (const FdSweep *)c->sweep, c->sweep_order, fd_args(c, s, dt_fd),
                        c->epoch + c->ncell, c->epoch, c->counters);
     timer_end(c, TK_FD);
     return check_hip(hipGetLastError());

@@ -107,6 +107,8 @@ struct sdpd_ctx {
     uint64_t *pairs;
     double *draws;               // 4 per pair entry: the sweep's random draws in sorted order
     void *sweep = nullptr;       // device table of the sweep kernel (fd.hip)
+    uint32_t *sweep_order = nullptr;   // hand-out order of the ranges inside each group
+    int tune_gen = 0;            // counts sdpd_tune calls (captured batches check it)
     size_t sweep_lds = 0;
     int sweep_grid = 0, sweep_ok = 0;
     uint32_t *epoch = nullptr;   // ncell + 1: per-cell group epochs, then the range counter

@@ -113,3 +113,21 @@ def test_batch_per_stream_graphs_match_eager_steps():
     r = subprocess.run([sys.executable, "-c", _PER_STREAM_CHILD, root], env=env, cwd=root,
                        capture_output=True, text=True, timeout=150)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout[-2000:] + r.stderr[-2000:]
+
+
+def test_batch_refuses_a_retuned_context():
+    import torch
+    from paper_1707_04232_amd import sdpd
+    say("batch after sdpd_tune")
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    bat = _boxes(2, 1, streams)
+    torch.cuda.synchronize()
+    with sdpd.Batch([c for c, _ in bat], [s for _, s in bat]) as B:
+        B.run(0, 1)
+        t = bat[0][0].get_tuning()
+        bat[0][0].tune(t["fd_tasks"], t["lds_particles"], t["lds_pairs"])
+        with pytest.raises(sdpd.SdpdError):
+            B.run(1, 1)
+    for c, _ in bat:
+        c.sync()
+        c.close()
