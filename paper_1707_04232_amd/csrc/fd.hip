@@ -576,7 +576,7 @@ constexpr Allow kAllow[4] = {
     {14.7, 10.0, 25.2, 20.0, 1.0},    // edge
     {6.7, 5.0, 5.4, 4.5, 1.0},        // corner
 };
-constexpr int kDefaultTasks[4] = {8, 8, 16, 48};
+constexpr int kDefaultTasks[4] = {8, 8, 16, 24};
 
 int round_up(double x, int q)
 {
