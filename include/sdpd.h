@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SDPD_ABI_VERSION 2
+#define SDPD_ABI_VERSION 3
 
 typedef enum {
     SDPD_OK = 0,
@@ -213,6 +213,21 @@ typedef struct {
 
 int sdpd_tune(sdpd_ctx *ctx, const sdpd_tuning *tuning);
 int sdpd_get_tuning(sdpd_ctx *ctx, sdpd_tuning *out);
+
+/* How the F/D sweep is launched (results are identical bit for bit).  The
+ * sweep is 27 groups of mutually disjoint phases (phase 0, then 26 groups of
+ * 4 inter-cell phases) that must follow one another on each cell.
+ *   SDPD_SWEEP_AUTO       one launch for boxes large enough to hold several
+ *                         GPU-fulls of task ranges, else one per group;
+ *   SDPD_SWEEP_ONE        one persistent launch: each range waits only for
+ *                         the ranges of the previous group on its cells;
+ *   SDPD_SWEEP_PER_GROUP  27 launches.
+ * Captured batches always use one launch per group.  sdpd_sweep_mode
+ * reports the layout in use (SDPD_SWEEP_ONE or SDPD_SWEEP_PER_GROUP) in
+ * *in_use when it is not NULL.  SDPD_EINVAL for another mode.             */
+enum { SDPD_SWEEP_AUTO = 0, SDPD_SWEEP_ONE = 1, SDPD_SWEEP_PER_GROUP = 2 };
+int sdpd_set_sweep_mode(sdpd_ctx *ctx, int mode);
+int sdpd_sweep_mode(sdpd_ctx *ctx, int *in_use);
 
 /* Batched replicas (many independent boxes advanced together).  Each box
  * is a context of its own (its parameters, replica index, stream) with its

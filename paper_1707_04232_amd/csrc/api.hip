@@ -530,4 +530,18 @@ int sdpd_get_tuning(sdpd_ctx *c, sdpd_tuning *out)
     return SDPD_OK;
 }
 
+int sdpd_set_sweep_mode(sdpd_ctx *c, int mode)
+{
+    if (!c || mode < SDPD_SWEEP_AUTO || mode > SDPD_SWEEP_PER_GROUP) return SDPD_EINVAL;
+    c->sweep_mode = mode;
+    return SDPD_OK;
+}
+
+int sdpd_sweep_mode(sdpd_ctx *c, int *in_use)
+{
+    if (!c) return SDPD_EINVAL;
+    if (in_use) *in_use = fd_one_launch(c) ? SDPD_SWEEP_ONE : SDPD_SWEEP_PER_GROUP;
+    return c->sweep_mode;
+}
+
 }  // extern "C"

@@ -7,7 +7,10 @@
 //     4 unless set): the streams then run side by side;
 //   * otherwise one graph for all boxes, the boxes' streams forked from and
 //     joined back into the batch's origin stream with events.
-// Either way each box keeps its own launch order.  The step index of the
+// Either way each box keeps its own launch order, and the F/D sweep is
+// captured as one launch per group: boxes that share the GPU would otherwise
+// hold workgroup slots while waiting on ranges of their own sweep that are
+// descheduled behind the other boxes' work.  The step index of the
 // random draws lives on the device: set once per run, advanced by every
 // replayed step, so one capture serves every step block.
 #include <stdlib.h>
@@ -120,8 +123,11 @@ int sdpd_batch_create(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
             }
             for (int k = 0; !rc && k < theta; ++k)
                 for (int j = 0; !rc && j < nbox; ++j)
-                    if (b->ctx[j]->stream == st)
+                    if (b->ctx[j]->stream == st) {
+                        b->ctx[j]->fd_per_group = 1;
                         rc = enqueue_step(b->ctx[j], &b->st[j], (uint64_t)k, false);
+                        b->ctx[j]->fd_per_group = 0;
+                    }
             hipGraph_t g = nullptr;
             const hipError_t ec = hipStreamEndCapture(st, &g);
             b->sgraph.push_back(g);
@@ -148,8 +154,11 @@ int sdpd_batch_create(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
     for (hipStream_t s : b->streams)
         if (!rc) rc = check_hip(hipStreamWaitEvent(s, b->fork, 0));
     for (int k = 0; !rc && k < theta; ++k)
-        for (int i = 0; !rc && i < nbox; ++i)
+        for (int i = 0; !rc && i < nbox; ++i) {
+            b->ctx[i]->fd_per_group = 1;
             rc = enqueue_step(b->ctx[i], &b->st[i], (uint64_t)k, false);
+            b->ctx[i]->fd_per_group = 0;
+        }
     for (size_t i = 0; !rc && i < b->streams.size(); ++i) {
         rc = check_hip(hipEventRecord(b->join[i], b->streams[i]));
         if (!rc) rc = check_hip(hipStreamWaitEvent(b->origin, b->join[i], 0));

@@ -105,18 +105,23 @@ __device__ __forceinline__ void fd_gather(const uint32_t *s_sorted, const uint32
     g.U = d23.y;
 }
 
-// Momenta and energies are the state that workgroups hand on to each other:
-// another workgroup of the same kernel, on any XCD, may have written them,
-// so they are read and written with agent-scope atomic loads and stores
-// (coherent across the XCDs' L2 caches, with no cache flush).
+// Momenta and energies are the state that workgroups hand on to each other.
+// COHERENT (the one-launch sweep): another workgroup of the same kernel, on
+// any XCD, may have written them, so they are read and written with
+// agent-scope atomic loads and stores (coherent across the XCDs' L2 caches,
+// with no cache flush); otherwise (one launch per group) plain accesses.
+template <bool COHERENT>
 __device__ __forceinline__ double state_load(const double *ptr)
 {
-    return __hip_atomic_load(ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (COHERENT) return __hip_atomic_load(ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *ptr;
 }
 
+template <bool COHERENT>
 __device__ __forceinline__ void state_store(double *ptr, double v)
 {
-    __hip_atomic_store(ptr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (COHERENT) __hip_atomic_store(ptr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *ptr = v;
 }
 
 // Arguments every range of the sweep reads or writes.
@@ -137,7 +142,7 @@ struct FdArgs {
 // consecutive tasks of one of its phases), staged, sorted, drawn and applied
 // level by level.  FAST: the common case (EMS, Lucy kernel, zeta = 0) fixed
 // at compile time.
-template <bool FAST>
+template <bool FAST, bool COHERENT>
 __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, int64_t b,
                                          unsigned char *lds, const FdArgs &A, FdCount &cnt,
                                          bool &negeps)
@@ -228,10 +233,10 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
                 if (l < np) {
                     const int64_t g = gl[r];
                     s_gidx[l] = (uint32_t)g;
-                    s_p[l] = state_load(p + g);
-                    s_p[CP + l] = state_load(p + n + g);
-                    s_p[2 * CP + l] = state_load(p + 2 * n + g);
-                    s_eps[l] = state_load(eps + g);
+                    s_p[l] = state_load<COHERENT>(p + g);
+                    s_p[CP + l] = state_load<COHERENT>(p + n + g);
+                    s_p[2 * CP + l] = state_load<COHERENT>(p + 2 * n + g);
+                    s_eps[l] = state_load<COHERENT>(eps + g);
                 }
             }
         }
@@ -415,10 +420,10 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
         // ---- write back momenta and energies
         for (int l = lane; l < np; l += 64) {
             const int64_t g = s_gidx[l];
-            state_store(p + g, s_p[l]);
-            state_store(p + n + g, s_p[CP + l]);
-            state_store(p + 2 * n + g, s_p[2 * CP + l]);
-            state_store(eps + g, s_eps[l]);
+            state_store<COHERENT>(p + g, s_p[l]);
+            state_store<COHERENT>(p + n + g, s_p[CP + l]);
+            state_store<COHERENT>(p + 2 * n + g, s_p[2 * CP + l]);
+            state_store<COHERENT>(eps + g, s_eps[l]);
         }
         __syncthreads();
     }
@@ -443,6 +448,18 @@ __device__ __forceinline__ void fd_flush_counters(const FdCount &cnt, bool negep
     }
 }
 
+// one launch per group: workgroup b = blockIdx.x applies range b of L
+template <bool FAST>
+__global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ Pp, FdLaunch L,
+                                                 FdArgs A, unsigned long long *counters)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    FdCount cnt = {0u, 0u, 0u, 0u, 0u};
+    bool negeps = false;
+    fd_range<FAST, false>(*Pp, L, (int64_t)blockIdx.x, lds, A, cnt, negeps);
+    fd_flush_counters(cnt, negeps, counters, A.err);
+}
+
 // The whole sweep in one launch.  Its ranges, group by group (group 0 =
 // phase 0, then the groups of mutually disjoint phases; inside a group in
 // the order of `order`), are handed out by an atomic counter, so a range is
@@ -451,8 +468,11 @@ __device__ __forceinline__ void fd_flush_counters(const FdCount &cnt, bool negep
 // cell exactly once, so epoch[c] = the number of groups done on cell c: a
 // range of group g waits until its cells have epoch g, and sets them to
 // g + 1 once its momenta and energies are written (stores completed first).
-// The wait is bounded: past kSpinLimit polls it reports ERR_STALL and goes
-// on, so every workgroup ends.
+// A wait normally lasts microseconds, but when many queues share the GPU a
+// workgroup holding a needed range can be descheduled for a long time (tens
+// of milliseconds were measured with 32 queues), so the wait is bounded in
+// time, not in polls: after kWaitTicks of the constant 100 MHz clock it
+// reports ERR_STALL and goes on, so every workgroup ends.
 constexpr int FD_MAXGROUPS = 32;
 struct FdSweep {
     int ngroups;
@@ -460,7 +480,7 @@ struct FdSweep {
     uint32_t group_end[FD_MAXGROUPS];   // cumulative ranges per group
     FdLaunch launch[FD_MAXGROUPS];
 };
-constexpr uint32_t kSpinLimit = 1u << 20;
+constexpr uint64_t kWaitTicks = 20ull * 100000000ull;   // 20 s
 
 template <bool FAST>
 __global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ Pp,
@@ -500,7 +520,8 @@ __global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ P
         }
         if (g > 0) {
             bool ready = lane >= R;
-            for (uint32_t spin = 0;; ++spin) {
+            const uint64_t t_wait = wall_clock64();
+            for (;;) {
                 if (!ready) {
                     const uint32_t ea =
                         __hip_atomic_load(epoch + cA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -510,7 +531,7 @@ __global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ P
                     ready = ea >= (uint32_t)g && eb >= (uint32_t)g;
                 }
                 if (__ballot(!ready) == 0ull) break;
-                if (spin >= kSpinLimit) {
+                if (wall_clock64() - t_wait > kWaitTicks) {
                     if (lane == 0) atomicOr(A.err, ERR_STALL);
                     break;
                 }
@@ -520,7 +541,7 @@ __global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ P
         // no memory access of the range moves above the wait (its state
         // loads are themselves coherent, so no cache invalidation is needed)
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        fd_range<FAST>(P, L, b, lds, A, cnt, negeps);
+        fd_range<FAST, true>(P, L, b, lds, A, cnt, negeps);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_s_waitcnt(0);   // the state stores have completed
         if (lane < R) {
@@ -608,7 +629,13 @@ void fd_default_tuning(sdpd_ctx *c)
     }
     if (c->max_lds > 65536) {
         // allow dynamic LDS beyond 64 KiB where the device has it
-        if (hipFuncSetAttribute((const void *)k_fd_sweep<false>,
+        if (hipFuncSetAttribute((const void *)k_fd_phase<false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                c->max_lds) != hipSuccess ||
+            hipFuncSetAttribute((const void *)k_fd_phase<true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                c->max_lds) != hipSuccess ||
+            hipFuncSetAttribute((const void *)k_fd_sweep<false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 c->max_lds) != hipSuccess ||
             hipFuncSetAttribute((const void *)k_fd_sweep<true>,
@@ -718,6 +745,30 @@ static FdArgs fd_args(const sdpd_ctx *c, const sdpd_state *s, double dt_fd)
 // launch size, rebuilt whenever the tuning changes.  The epochs need every
 // group to touch every cell exactly once: its phases' parity sets partition
 // the 8 parities (true of the 26 groups of the 13 forward offsets; checked).
+bool fd_one_launch(const sdpd_ctx *c)
+{
+    if (c->fd_per_group || c->sweep_mode == SDPD_SWEEP_PER_GROUP) return false;
+    return c->sweep_mode == SDPD_SWEEP_ONE || c->fd_dataflow;
+}
+
+// one launch per group
+static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, int nph,
+                         double dt_fd)
+{
+    FdLaunch L;
+    const int64_t wg = fd_launch_geometry(c, phases, nph, L);
+    if (wg == 0) return SDPD_OK;
+    if (wg > 0x7fffffffLL) return SDPD_EINVAL;
+    const size_t lds = fd_lds_bytes(L.cap_p, L.cap_e);
+    if (lds > (size_t)c->max_lds) return SDPD_EINVAL;
+    timer_begin(c, TK_FD);
+    auto kern = fd_fast(c) ? k_fd_phase<true> : k_fd_phase<false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)wg), dim3(64), lds, c->stream, c->dparams, L,
+                       fd_args(c, s, dt_fd), c->counters);
+    timer_end(c, TK_FD);
+    return check_hip(hipGetLastError());
+}
+
 // cells of task T (the host form of task_cells); B = -1 for a phase-0 task
 static void task_cells_host(const sdpd_ctx *c, int64_t T, int64_t &A, int64_t &B)
 {
@@ -844,6 +895,10 @@ int fd_prepare_sweep(sdpd_ctx *c)
     }
     c->sweep_lds = lds;
     c->sweep_grid = (int)std::min<int64_t>((int64_t)per_cu * cus, std::max<int64_t>(total, 1));
+    // one launch when the sweep holds several GPU-fulls of ranges; a small box
+    // would mostly wait on its chain of 27 groups, and one launch per group
+    // then wastes no workgroup slots on waiting
+    c->fd_dataflow = total >= 4 * (int64_t)per_cu * cus;
     c->sweep_ok = 1;
     return SDPD_OK;
 }
@@ -876,6 +931,11 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
     if ((rc = check_hip(hipGetLastError()))) return rc;
     c->fd_swept = 1;
     if (!c->sweep_ok) return SDPD_EINVAL;
+    if (!fd_one_launch(c)) {
+        for (const std::vector<int> &g : fd_groups())
+            if ((rc = launch_phases(c, s, g.data(), (int)g.size(), dt_fd))) return rc;
+        return SDPD_OK;
+    }
     // epochs of the cells and the range counter start at zero
     if ((rc = launch_fill_u32(c, c->epoch, 0u, c->ncell + 1))) return rc;
     timer_begin(c, TK_FD);
@@ -885,7 +945,6 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
                        c->epoch + c->ncell, c->epoch, c->counters);
     timer_end(c, TK_FD);
     return check_hip(hipGetLastError());
-    return SDPD_OK;
 }
 
 }  // namespace sdpd

@@ -109,6 +109,9 @@ struct sdpd_ctx {
     void *sweep = nullptr;       // device table of the sweep kernel (fd.hip)
     uint32_t *sweep_order = nullptr;   // hand-out order of the ranges inside each group
     int tune_gen = 0;            // counts sdpd_tune calls (captured batches check it)
+    int fd_dataflow = 0;         // SDPD_SWEEP_AUTO chooses one launch (large boxes)
+    int fd_per_group = 0;        // force one launch per group (set while a batch captures)
+    int sweep_mode = 0;          // SDPD_SWEEP_*
     size_t sweep_lds = 0;
     int sweep_grid = 0, sweep_ok = 0;
     uint32_t *epoch = nullptr;   // ncell + 1: per-cell group epochs, then the range counter
@@ -142,6 +145,7 @@ int enqueue_step(sdpd_ctx *c, const sdpd_state *s, uint64_t step, bool set_step)
 void fd_default_tuning(sdpd_ctx *c);
 int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t);
 int fd_prepare_sweep(sdpd_ctx *c);   // after any change of the tuning
+bool fd_one_launch(const sdpd_ctx *c);   // the sweep runs as one launch
 int run_observe(sdpd_ctx *c, const sdpd_state *s, double *dst_record);
 void adjoint_free(AdjointWork *a);
 

@@ -17,13 +17,15 @@ OK, EINVAL, EHIP, ENOMEM, ECELLCAP, ENEGEPS, ENONFINITE, ECAPACITY = 0, -1, -2, 
 KERNEL_LUCY, KERNEL_CUBIC = 0, 1
 FD_EMS, FD_AMS, FD_SSA, FD_NONE = 0, 1, 2, 3
 FP64, MIXED = 0, 1
+SWEEP_AUTO, SWEEP_ONE, SWEEP_PER_GROUP = 0, 1, 2
 TIMING_CLASSES = ("cells", "density", "fd", "forces", "observe", "schedule")
 
 EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
            "sdpd_copy_cell_start", "sdpd_density",
            "sdpd_forces", "sdpd_fd_metropolis", "sdpd_step", "sdpd_observe", "sdpd_sync",
            "sdpd_set_timing", "sdpd_timing", "sdpd_tune", "sdpd_get_tuning",
-           "sdpd_fd_schedule_size", "sdpd_batch_create", "sdpd_batch_run",
+           "sdpd_fd_schedule_size", "sdpd_set_sweep_mode", "sdpd_sweep_mode",
+           "sdpd_batch_create", "sdpd_batch_run",
            "sdpd_batch_destroy", "sdpd_adjoint_forward", "sdpd_adjoint_backward",
            "sdpd_strerror",
            "sdpd_abi_version")
@@ -310,6 +312,18 @@ class Context:
         _check(lib().sdpd_get_tuning(self._h, C.byref(t)), "sdpd_get_tuning")
         return {"fd_tasks": tuple(t.fd_tasks), "lds_particles": tuple(t.fd_lds_particles),
                 "lds_pairs": tuple(t.fd_lds_pairs)}
+
+    def set_sweep_mode(self, mode: int):
+        """SWEEP_AUTO, SWEEP_ONE or SWEEP_PER_GROUP (results are identical)."""
+        _check(lib().sdpd_set_sweep_mode(self._h, int(mode)), "sdpd_set_sweep_mode")
+
+    def sweep_mode(self) -> tuple:
+        """(mode set, layout in use)."""
+        u = C.c_int(0)
+        m = lib().sdpd_sweep_mode(self._h, C.byref(u))
+        if m < 0:
+            _check(m, "sdpd_sweep_mode")
+        return m, u.value
 
     def prepare(self, s: DeviceState):
         """cells, density without energy update, forces: the entry state of step()."""

@@ -149,12 +149,16 @@ def _fd_case(dims, Cv, T, dt, mode, kernel, zeta, jitter=0.05):
     return both(q, p, eps, ids, box, Cv=Cv, dt=dt, fd=mode, kernel=kernel, zeta=zeta)
 
 
+@pytest.mark.parametrize("sweep", ["one", "per_group"])
 @pytest.mark.parametrize("name,dims,Cv,T,dt,mode,kernel,zeta", FD_CASES,
                          ids=[c[0] for c in FD_CASES])
-def test_fd_sweep_parity(name, dims, Cv, T, dt, mode, kernel, zeta):
-    say("fd sweep", name)
+def test_fd_sweep_parity(name, dims, Cv, T, dt, mode, kernel, zeta, sweep):
+    say("fd sweep", name, sweep)
     gp, op, S, R = _fd_case(dims, Cv, T, dt, mode, kernel, zeta)
-    with sd().Context(gp) as ctx:
+    sdpd = sd()
+    with sdpd.Context(gp) as ctx:
+        ctx.set_sweep_mode(sdpd.SWEEP_ONE if sweep == "one" else sdpd.SWEEP_PER_GROUP)
+        assert ctx.sweep_mode()[1] == (sdpd.SWEEP_ONE if sweep == "one" else sdpd.SWEEP_PER_GROUP)
         ctx.prepare(S)
         gst = ctx.fd_metropolis(S, step=7)
     O.prepare(op, R)
@@ -168,9 +172,11 @@ def test_fd_sweep_parity(name, dims, Cv, T, dt, mode, kernel, zeta):
         assert gst["rej_energy"] + gst["rej_ratio"] > 0
 
 
-def test_fd_sweep_tuning_does_not_change_results():
-    say("fd sweep tuning invariance")
+@pytest.mark.parametrize("sweep", ["one", "per_group"])
+def test_fd_sweep_tuning_does_not_change_results(sweep):
+    say("fd sweep tuning invariance", sweep)
     sdpd = sd()
+    want = sdpd.SWEEP_ONE if sweep == "one" else sdpd.SWEEP_PER_GROUP
     outs = []
     configs = [
         None,                                                    # defaults
@@ -184,10 +190,12 @@ def test_fd_sweep_tuning_does_not_change_results():
     for cfg in configs:
         gp, op, S, R = _fd_case((24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0)
         with sd().Context(gp) as ctx:
+            ctx.set_sweep_mode(want)
             if cfg:
                 ctx.tune(**cfg)
                 t = ctx.get_tuning()
                 assert t["fd_tasks"] == cfg["fd_tasks"]
+            assert ctx.sweep_mode() == (want, want)
             ctx.prepare(S)
             ctx.fd_metropolis(S, step=3)
         outs.append(S.to_numpy())
