@@ -3,6 +3,8 @@
 #include "sdpd_internal.hpp"
 #include "fd_elem.hpp"
 
+#include <float.h>
+
 namespace sdpd {
 
 // W(r) for r < h (Sec. 2.1.1; Lucy's kernel or the cubic spline of
@@ -34,7 +36,8 @@ __device__ __forceinline__ uint64_t density_cell(const DevParams &P, const doubl
         }
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < P.h2) {
-            acc += P.m * kernel_w(P, r2 > 0.0 ? fd_sqrt(r2) : 0.0);   // r = 0: i itself
+            // r = 0 (i itself): sqrt(DBL_MIN) gives the same W as r = 0, exactly
+            acc += P.m * kernel_w(P, fd_sqrt(fmax(r2, DBL_MIN)));
             mask |= bit;
         }
     }
@@ -67,8 +70,9 @@ __global__ __launch_bounds__(256) void k_density(DevParams P, const double *__re
     const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
     const double xi = q4[4 * i], yi = q4[4 * i + 1], zi = q4[4 * i + 2];
     double acc = 0.0;
+    const NbSteps steps(P, cx, cy, cz);
     for (int k = 0; k < 27; ++k) {
-        const NbCell nb = neighbour_cell(P, cx, cy, cz, k);
+        const NbCell nb = steps.get(P, k);
         const uint32_t s = cell_start[nb.c], e = cell_start[nb.c + 1];
         uint64_t mask = 0;
         if (e - s > (uint32_t)P.cap) {   // overflowing cell: reported, not visited

@@ -3,6 +3,8 @@
 #include "sdpd_internal.hpp"
 #include "fd_elem.hpp"
 
+#include <float.h>
+
 namespace sdpd {
 
 // F(r) with grad W(r) = -F(|r|) r, for 0 < r < h (Sec. 2.1.1; the cubic
@@ -67,7 +69,8 @@ __global__ __launch_bounds__(256) void k_forces(DevParams P, const double *__res
             const double dy = (yi - qj.y) + nb.sy;
             const double dz = (zi - qj.z) + nb.sz;
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const double sc = m2 * (pii + qj.w) * kernel_f(P, r2 > 0.0 ? fd_sqrt(r2) : 0.0);
+            // coincident particles (r = 0): F(sqrt(DBL_MIN)) = F(0) and dx = 0
+            const double sc = m2 * (pii + qj.w) * kernel_f(P, fd_sqrt(fmax(r2, DBL_MIN)));
             fx += sc * dx;
             fy += sc * dy;
             fz += sc * dz;
