@@ -142,10 +142,14 @@ struct FdArgs {
 // consecutive tasks of one of its phases), staged, sorted, drawn and applied
 // level by level.  FAST: the common case (EMS, Lucy kernel, zeta = 0) fixed
 // at compile time.
-template <bool FAST, bool COHERENT>
+// wait() is called once, before the first access to momenta and energies:
+// everything before it (entries, lists, ids, positions, the draws) is fixed
+// during the sweep, so the level sort and the draws of a range overlap the
+// wait for its predecessors.
+template <bool FAST, bool COHERENT, class Wait>
 __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, int64_t b,
                                          unsigned char *lds, const FdArgs &A, FdCount &cnt,
-                                         bool &negeps)
+                                         bool &negeps, Wait &wait)
 {
     const double4 *__restrict__ qrho = A.qrho;
     double *p = A.p, *eps = A.eps;
@@ -217,9 +221,7 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
         const int npr = (int)(s_eoff[k] - e_begin), np = (int)(s_poff[k] - p_begin);
         if (npr == 0) continue;
         const uint32_t rel0 = p_begin - phase_p0;   // list position of batch particle 0
-        // ---- stage momenta and energies of the particles that take part in
-        //      a pair: list entries first (one round-trip per pass), then the
-        //      state loads
+        // ---- global indices of the particles that take part in a pair
         for (int base = 0; base < np; base += FD_PPL * 64) {
             uint32_t gl[FD_PPL];
 #pragma unroll
@@ -230,16 +232,11 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
 #pragma unroll
             for (int r = 0; r < FD_PPL; ++r) {
                 const int l = base + r * 64 + lane;
-                if (l < np) {
-                    const int64_t g = gl[r];
-                    s_gidx[l] = (uint32_t)g;
-                    s_p[l] = state_load<COHERENT>(p + g);
-                    s_p[CP + l] = state_load<COHERENT>(p + n + g);
-                    s_p[2 * CP + l] = state_load<COHERENT>(p + 2 * n + g);
-                    s_eps[l] = state_load<COHERENT>(eps + g);
-                }
+                if (l < np) s_gidx[l] = gl[r];
             }
         }
+        __syncthreads();
+        bool staged = false;   // momenta and energies of the batch in LDS
         // ---- windows of levels (one window unless a single task overflows
         //      the LDS pair list; then consecutive level ranges that fit)
         int lo = 1;
@@ -363,6 +360,26 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
                 }
             }
             __syncthreads();
+            if (!staged) {
+                // ---- stage momenta and energies (after the wait for the
+                //      range's predecessors, on the first batch)
+                wait();
+                for (int base = 0; base < np; base += FD_PPL * 64) {
+#pragma unroll
+                    for (int r = 0; r < FD_PPL; ++r) {
+                        const int l = base + r * 64 + lane;
+                        if (l < np) {
+                            const int64_t g = s_gidx[l];
+                            s_p[l] = state_load<COHERENT>(p + g);
+                            s_p[CP + l] = state_load<COHERENT>(p + n + g);
+                            s_p[2 * CP + l] = state_load<COHERENT>(p + 2 * n + g);
+                            s_eps[l] = state_load<COHERENT>(eps + g);
+                        }
+                    }
+                }
+                staged = true;
+                __syncthreads();
+            }
             // level steps: (level, first sorted position) in ascending order;
             // the read-only data of steps k + 1 and k + 2 is in flight while
             // step k runs (the gathers only read LDS entries fixed above)
@@ -418,7 +435,7 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
             if (!oversized) break;
         }
         // ---- write back momenta and energies
-        for (int l = lane; l < np; l += 64) {
+        for (int l = lane; staged && l < np; l += 64) {
             const int64_t g = s_gidx[l];
             state_store<COHERENT>(p + g, s_p[l]);
             state_store<COHERENT>(p + n + g, s_p[CP + l]);
@@ -456,7 +473,8 @@ __global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ P
     extern __shared__ __align__(16) unsigned char lds[];
     FdCount cnt = {0u, 0u, 0u, 0u, 0u};
     bool negeps = false;
-    fd_range<FAST, false>(*Pp, L, (int64_t)blockIdx.x, lds, A, cnt, negeps);
+    auto no_wait = [] {};
+    fd_range<FAST, false>(*Pp, L, (int64_t)blockIdx.x, lds, A, cnt, negeps, no_wait);
     fd_flush_counters(cnt, negeps, counters, A.err);
 }
 
@@ -518,30 +536,39 @@ __global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ P
             cA = tc.A;
             cB = tc.slot == 0 ? -1 : tc.B;
         }
-        if (g > 0) {
-            bool ready = lane >= R;
-            const uint64_t t_wait = wall_clock64();
-            for (;;) {
-                if (!ready) {
-                    const uint32_t ea =
-                        __hip_atomic_load(epoch + cA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const uint32_t eb = cB < 0 ? (uint32_t)g
-                                               : __hip_atomic_load(epoch + cB, __ATOMIC_RELAXED,
-                                                                   __HIP_MEMORY_SCOPE_AGENT);
-                    ready = ea >= (uint32_t)g && eb >= (uint32_t)g;
+        bool waited = false;
+        auto wait = [&] {
+            if (waited) return;
+            waited = true;
+            if (g > 0) {
+                bool ready = lane >= R;
+                const uint64_t t_wait = wall_clock64();
+                for (;;) {
+                    if (!ready) {
+                        const uint32_t ea = __hip_atomic_load(epoch + cA, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+                        const uint32_t eb =
+                            cB < 0 ? (uint32_t)g
+                                   : __hip_atomic_load(epoch + cB, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                        ready = ea >= (uint32_t)g && eb >= (uint32_t)g;
+                    }
+                    if (__ballot(!ready) == 0ull) break;
+                    if (wall_clock64() - t_wait > kWaitTicks) {
+                        if (lane == 0) atomicOr(A.err, ERR_STALL);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
                 }
-                if (__ballot(!ready) == 0ull) break;
-                if (wall_clock64() - t_wait > kWaitTicks) {
-                    if (lane == 0) atomicOr(A.err, ERR_STALL);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
             }
-        }
-        // no memory access of the range moves above the wait (its state
-        // loads are themselves coherent, so no cache invalidation is needed)
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        fd_range<FAST, true>(P, L, b, lds, A, cnt, negeps);
+            // no state access of the range moves above the wait (the state
+            // loads are themselves coherent, so no cache invalidation is
+            // needed)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        };
+        fd_range<FAST, true>(P, L, b, lds, A, cnt, negeps, wait);
+        // a range without pairs still orders its cells behind the predecessors
+        wait();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_s_waitcnt(0);   // the state stores have completed
         if (lane < R) {

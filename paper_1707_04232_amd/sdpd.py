@@ -74,6 +74,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -c 'import __graft_entry__; __graft_entry__.build()'`")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded (one runtime per process; loading the library first made
+        # torch and the library disagree about the device)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, u64 = C.c_void_p, C.c_int, C.c_int64, C.c_uint64
         SP = C.POINTER(_State)
