@@ -222,9 +222,11 @@ int sdpd_get_tuning(sdpd_ctx *ctx, sdpd_tuning *out);
  *   SDPD_SWEEP_ONE        one persistent launch: each range waits only for
  *                         the ranges of the previous group on its cells;
  *   SDPD_SWEEP_PER_GROUP  27 launches.
- * Captured batches always use one launch per group.  sdpd_sweep_mode
- * reports the layout in use (SDPD_SWEEP_ONE or SDPD_SWEEP_PER_GROUP) in
- * *in_use when it is not NULL.  SDPD_EINVAL for another mode.             */
+ * Captured batches always use one launch per group.  sdpd_set_sweep_mode
+ * returns SDPD_EINVAL for another mode or a NULL context.  sdpd_sweep_mode
+ * returns the mode set (>= 0; SDPD_EINVAL for a NULL context) and writes
+ * the layout the next sweep uses (SDPD_SWEEP_ONE or SDPD_SWEEP_PER_GROUP)
+ * to *in_use when it is not NULL.                                          */
 enum { SDPD_SWEEP_AUTO = 0, SDPD_SWEEP_ONE = 1, SDPD_SWEEP_PER_GROUP = 2 };
 int sdpd_set_sweep_mode(sdpd_ctx *ctx, int mode);
 int sdpd_sweep_mode(sdpd_ctx *ctx, int *in_use);
