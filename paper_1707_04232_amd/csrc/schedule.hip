@@ -21,18 +21,21 @@
 
 namespace sdpd {
 
-// pairs and participating particles of every task: one 32-lane half-wave
-// per task, lane x reading the masks of slots x, x + 32 of cell A, then
-// sums and ORs over the half-wave (all mask loads of a task in flight at once)
-constexpr int COUNT_WAVES = 4;   // waves per workgroup, two tasks per wave
+// pairs and participating particles of every task: one 16-lane quarter-wave
+// per task (a cell holds 16 particles on average), lane x reading the masks
+// of slots x, x + 16, ... of cell A, then sums and ORs over the quarter
+// (all mask loads of a task in flight at once)
+constexpr int COUNT_WAVES = 4;     // waves per workgroup
+constexpr int COUNT_LANES = 16;    // lanes per task: four tasks per wave
 
 __global__ __launch_bounds__(64 * COUNT_WAVES) void k_task_count(
     const DevParams *__restrict__ Pp, const uint32_t *__restrict__ cell_start,
     const uint64_t *__restrict__ masks, uint32_t *tcount, uint32_t *tnp)
 {
     const DevParams &P = *Pp;
-    const int lane = threadIdx.x & 63, x = lane & 31;
-    const int64_t T = ((int64_t)blockIdx.x * COUNT_WAVES + (threadIdx.x >> 6)) * 2 + (lane >> 5);
+    const int lane = threadIdx.x & 63, x = lane & (COUNT_LANES - 1);
+    const int64_t T = ((int64_t)blockIdx.x * COUNT_WAVES + (threadIdx.x >> 6)) * (64 / COUNT_LANES) +
+                      lane / COUNT_LANES;
     const bool ok = T < (int64_t)NMASK * P.ncell;
     uint32_t c = 0, na = 0;
     uint64_t orb = 0;
@@ -43,7 +46,7 @@ __global__ __launch_bounds__(64 * COUNT_WAVES) void k_task_count(
         const uint32_t sA = cell_start[tc.A], nA = cell_start[tc.A + 1] - sA;
         const uint32_t nB = cell_start[tc.B + 1] - cell_start[tc.B];
         if (nA <= (uint32_t)P.cap && nB <= (uint32_t)P.cap) {
-            for (uint32_t a = (uint32_t)x; a < nA; a += 32) {
+            for (uint32_t a = (uint32_t)x; a < nA; a += COUNT_LANES) {
                 const uint64_t m = masks[(int64_t)(OWN_NB + tc.slot) * P.n + sA + a];
                 na += m != 0ull;
                 orb |= m;
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(64 * COUNT_WAVES) void k_task_count(
         }
     }
 #pragma unroll
-    for (int off = 16; off > 0; off >>= 1) {   // stays inside the half-wave
+    for (int off = COUNT_LANES / 2; off > 0; off >>= 1) {   // stays inside the quarter
         c += (uint32_t)__shfl_xor((int)c, off);
         na += (uint32_t)__shfl_xor((int)na, off);
         orb |= (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)orb, off) |
@@ -241,7 +244,8 @@ int run_schedule(sdpd_ctx *c)
 {
     const int64_t ntask = (int64_t)NMASK * c->ncell;
     timer_begin(c, TK_SCHED);
-    const int64_t count_blocks = (ntask + 2 * COUNT_WAVES - 1) / (2 * COUNT_WAVES);
+    const int64_t per_block = (int64_t)COUNT_WAVES * (64 / COUNT_LANES);
+    const int64_t count_blocks = (ntask + per_block - 1) / per_block;
     hipLaunchKernelGGL(k_task_count, dim3((unsigned)count_blocks), dim3(64 * COUNT_WAVES), 0,
                        c->stream, c->dparams, c->cell_start, c->masks, c->task_count, c->task_np);
     int rc = check_hip(hipGetLastError());
