@@ -225,12 +225,32 @@ __global__ void k_gather(DevParams P, int64_t n, const uint32_t *perm, const uin
     for (int c = 0; c < 3; ++c) {
         tq[c * n + k] = q[c * n + i];
         tp[c * n + k] = p[c * n + i];
-        tf[c * n + k] = f[c * n + i];
+        if (tf) tf[c * n + k] = f[c * n + i];
     }
     teps[k] = eps[i];
     trho[k] = rho[i];
     tid[k] = id[i];
     cell_sorted[k] = cell_of[i];
+}
+
+// the sorted arrays back into the caller's state, one launch (f only when
+// it was gathered)
+__global__ void k_copy_back(int64_t n, const double *tq, const double *tp, const double *tf,
+                            const double *teps, const double *trho, const uint32_t *tid,
+                            double *q, double *p, double *f, double *eps, double *rho,
+                            uint32_t *id)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        q[c * n + k] = tq[c * n + k];
+        p[c * n + k] = tp[c * n + k];
+        if (tf) f[c * n + k] = tf[c * n + k];
+    }
+    eps[k] = teps[k];
+    rho[k] = trho[k];
+    id[k] = tid[k];
 }
 
 static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -281,26 +301,15 @@ int run_build_cells(sdpd_ctx *c, const sdpd_state *s, int kick_drift)
                            c->cursor, c->tmp_idx, n);
         hipLaunchKernelGGL(k_rank, dim3(g), dim3(256), 0, c->stream, c->tmp_idx, c->cell_of,
                            c->cell_start, s->id, c->perm, n, c->prm.cell_cap);
+        // inside a step (kick_drift) the forces are recomputed before
+        // anything reads them, so they are not carried through the sort
+        double *tf = kick_drift ? nullptr : c->tf;
         hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, c->dp, n, c->perm,
                            c->cell_of, s->q, s->p, s->eps, s->rho, s->f, s->id, c->tq, c->tp,
-                           c->teps, c->trho, c->tf, c->tid, c->cell_sorted, c->qr, c->q4);
+                           c->teps, c->trho, tf, c->tid, c->cell_sorted, c->qr, c->q4);
+        hipLaunchKernelGGL(k_copy_back, dim3(g), dim3(256), 0, c->stream, n, c->tq, c->tp, tf,
+                           c->teps, c->trho, c->tid, s->q, s->p, s->f, s->eps, s->rho, s->id);
         if ((rc = check_hip(hipGetLastError()))) return rc;
-        const size_t d3 = sizeof(double) * 3 * (size_t)n, d1 = sizeof(double) * (size_t)n;
-        if ((rc = check_hip(hipMemcpyAsync(s->q, c->tq, d3, hipMemcpyDeviceToDevice, c->stream))))
-            return rc;
-        if ((rc = check_hip(hipMemcpyAsync(s->p, c->tp, d3, hipMemcpyDeviceToDevice, c->stream))))
-            return rc;
-        if ((rc = check_hip(hipMemcpyAsync(s->f, c->tf, d3, hipMemcpyDeviceToDevice, c->stream))))
-            return rc;
-        if ((rc = check_hip(hipMemcpyAsync(s->eps, c->teps, d1, hipMemcpyDeviceToDevice,
-                                           c->stream))))
-            return rc;
-        if ((rc = check_hip(hipMemcpyAsync(s->rho, c->trho, d1, hipMemcpyDeviceToDevice,
-                                           c->stream))))
-            return rc;
-        if ((rc = check_hip(hipMemcpyAsync(s->id, c->tid, sizeof(uint32_t) * (size_t)n,
-                                           hipMemcpyDeviceToDevice, c->stream))))
-            return rc;
     }
     timer_end(c, TK_CELLS);
     c->cells_valid = 1;

@@ -46,6 +46,8 @@ def test_full_size_step_parity():
     gp, op = _params(sdpd, w, sdpd.FD_EMS)
     S = sdpd.DeviceState.from_numpy(q, p, eps, ids)
     with sdpd.Context(gp) as ctx:
+        # the benchmark's launch configuration: one dataflow launch per sweep
+        assert ctx.sweep_mode() == (sdpd.SWEEP_AUTO, sdpd.SWEEP_ONE)
         ctx.prepare(S)
         ctx.step(S, 0, 3)
         h = S.to_numpy()

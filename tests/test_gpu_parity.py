@@ -172,6 +172,21 @@ def test_fd_sweep_parity(name, dims, Cv, T, dt, mode, kernel, zeta, sweep):
         assert gst["rej_energy"] + gst["rej_ratio"] > 0
 
 
+def test_small_box_sweeps_per_group_by_default():
+    # a box with few task ranges waits mostly on its chain of groups: the
+    # automatic choice launches per group; both layouts can be forced
+    sdpd = sd()
+    gp, op, S, R = _fd_case((24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0)
+    with sdpd.Context(gp) as ctx:
+        assert ctx.sweep_mode() == (sdpd.SWEEP_AUTO, sdpd.SWEEP_PER_GROUP)
+        ctx.set_sweep_mode(sdpd.SWEEP_ONE)
+        assert ctx.sweep_mode() == (sdpd.SWEEP_ONE, sdpd.SWEEP_ONE)
+        with pytest.raises(sdpd.SdpdError) as e:
+            ctx.set_sweep_mode(3)
+        assert e.value.rc == sdpd.EINVAL
+        assert ctx.sweep_mode() == (sdpd.SWEEP_ONE, sdpd.SWEEP_ONE)
+
+
 @pytest.mark.parametrize("sweep", ["one", "per_group"])
 def test_fd_sweep_tuning_does_not_change_results(sweep):
     say("fd sweep tuning invariance", sweep)
