@@ -395,13 +395,15 @@ int enqueue_step(sdpd_ctx *c, const sdpd_state *s, uint64_t step, bool set_step)
     int rc;
     const uint64_t theta = (uint64_t)c->prm.fd_every;
     if ((rc = run_build_cells(c, s, 1))) return rc;
-    if ((rc = run_density(c, s, 1))) return rc;
+    // FP64: the density pass leaves (x, y, z, rho) packed for the sweep
+    const bool packed = !c->dp.mixed;
+    if ((rc = run_density(c, s, 1, packed))) return rc;
     if ((rc = launch_fill_u64(c, c->counters, 0ull, CNT_N))) return rc;
     if (step % theta == 0) {
         if (set_step &&
             (rc = launch_fill_u64(c, (unsigned long long *)c->dstep, step, 1)))
             return rc;
-        if ((rc = run_fd_sweep(c, s, c->prm.dt * (double)theta))) return rc;
+        if ((rc = run_fd_sweep(c, s, c->prm.dt * (double)theta, packed))) return rc;
     }
     if ((rc = run_forces(c, s, 1))) return rc;
     if (!set_step && (rc = launch_incr_u64(c, (unsigned long long *)c->dstep))) return rc;

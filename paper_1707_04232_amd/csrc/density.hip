@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_density(DevParams P, const double *__re
                                                  const uint32_t *__restrict__ cell_start,
                                                  double *rho, double *eps, int update_eps,
                                                  uint64_t *__restrict__ masks,
-                                                 uint32_t *err)
+                                                 uint32_t *err, double *rho_w)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
@@ -90,6 +90,9 @@ __global__ __launch_bounds__(256) void k_density(DevParams P, const double *__re
     }
     const double rho_old = rho[i];
     rho[i] = acc;
+    // also into the w slot of the particle's packed record (never read in
+    // this pass), where the fluctuation/dissipation sweep reads it
+    if (rho_w) rho_w[4 * i + 3] = acc;
     if (update_eps) {
         double e_new = eps[i] * pow(acc / rho_old, P.eps_exp);
         if (!(e_new > 0.0) || !isfinite(e_new)) atomicOr(err, ERR_NONFINITE);
@@ -97,7 +100,7 @@ __global__ __launch_bounds__(256) void k_density(DevParams P, const double *__re
     }
 }
 
-int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps)
+int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps, bool pack_rho)
 {
     if (c->n == 0) {
         c->masks_valid = 1;
@@ -111,7 +114,7 @@ int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps)
     timer_begin(c, TK_DENSITY);
     hipLaunchKernelGGL(k_density, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, c->stream,
                        c->dp, c->q4, c->cell_sorted, c->cell_start, s->rho, s->eps, update_eps,
-                       c->masks, c->err);
+                       c->masks, c->err, pack_rho ? c->q4 : nullptr);
     int rc = check_hip(hipGetLastError());
     timer_end(c, TK_DENSITY);
     if (!rc) c->masks_valid = 1;

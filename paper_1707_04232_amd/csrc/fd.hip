@@ -946,16 +946,18 @@ __global__ void k_pack_qrho(int64_t n, const double *__restrict__ q,
 
 // The step index of the draws is read from c->dstep on the device (set by
 // the caller, or advanced inside a captured graph).
-int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
+int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd, bool packed)
 {
     if (c->prm.fd == SDPD_FD_NONE || c->n == 0) return SDPD_OK;
     int rc = run_schedule(c);
     if (rc) return rc;
-    timer_begin(c, TK_SCHED);   // sweep preparation, with the schedule
-    hipLaunchKernelGGL(k_pack_qrho, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, c->stream,
-                       c->n, s->q, s->rho, reinterpret_cast<double4 *>(c->q4));
-    timer_end(c, TK_SCHED);
-    if ((rc = check_hip(hipGetLastError()))) return rc;
+    if (!packed) {
+        timer_begin(c, TK_SCHED);   // sweep preparation, with the schedule
+        hipLaunchKernelGGL(k_pack_qrho, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0,
+                           c->stream, c->n, s->q, s->rho, reinterpret_cast<double4 *>(c->q4));
+        timer_end(c, TK_SCHED);
+        if ((rc = check_hip(hipGetLastError()))) return rc;
+    }
     c->fd_swept = 1;
     if (!c->sweep_ok) return SDPD_EINVAL;
     if (!fd_one_launch(c)) {

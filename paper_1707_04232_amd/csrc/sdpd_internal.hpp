@@ -136,11 +136,15 @@ int run_scan(sdpd_ctx *c, const uint32_t *in, uint32_t *out, int64_t count, uint
              int cap);
 int run_schedule(sdpd_ctx *c);
 int run_build_cells(sdpd_ctx *c, const sdpd_state *s, int kick_drift);
-int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps);
+// pack_rho: also write rho into the w slot of the packed position records,
+// where a sweep that follows in the same step reads it (FP64 path)
+int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps, bool pack_rho = false);
 int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick);
 int run_density_f32(sdpd_ctx *c, const sdpd_state *s, int update_eps);
 int run_forces_f32(sdpd_ctx *c, const sdpd_state *s, int half_kick);
-int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd);
+// packed: the (x, y, z, rho) records are already in place (a density pass
+// with pack_rho ran since the cells were built)
+int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd, bool packed = false);
 int enqueue_step(sdpd_ctx *c, const sdpd_state *s, uint64_t step, bool set_step);
 void fd_default_tuning(sdpd_ctx *c);
 int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t);
