@@ -117,6 +117,24 @@ def replicas_bench(args):
     torch.cuda.synchronize()
     print(f"# replicas: {nbox} boxes, {n_tot} particles, sides {min(b[0] for b in boxes)}.."
           f"{max(b[0] for b in boxes)}", file=sys.stderr, flush=True)
+    tuned = None
+    if args.autotune:
+        # the library's autotuner on the largest box of each size class (sides
+        # in bands of 7 sites); its tuning is then given to every box of the class
+        t0 = time.perf_counter()
+        classes = {}
+        for b, (side, _, _) in enumerate(boxes):
+            classes.setdefault((side - 13) // 7, []).append(b)
+        tuned = {}
+        for cl, members in sorted(classes.items()):
+            lead = max(members, key=lambda b: boxes[b][0])
+            t = ctxs[lead].autotune(states[lead], trials=3)
+            for b in members:
+                ctxs[b].tune(t["fd_tasks"], t["lds_particles"], t["lds_pairs"])
+            tuned[f"sides {13 + 7 * cl}..{19 + 7 * cl}"] = t["fd_tasks"]
+        torch.cuda.synchronize()
+        tuned = {"fd_tasks": tuned, "seconds": time.perf_counter() - t0}
+        print(f"# autotuned {tuned}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     B = sdpd.Batch(ctxs, states)
     t_capture = time.perf_counter() - t0
@@ -158,6 +176,7 @@ def replicas_bench(args):
                              "ms_per_step": 1e3 * el_eager / neager},
         "graph_speedup": (n_tot * args.steps / el) / (n_tot * neager / el_eager),
         "capture_s": t_capture,
+        "autotune": tuned,
         "sum_E_final": float(np.sum(E)),
     }
     print(json.dumps(out), flush=True)
@@ -245,6 +264,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--streams", type=int, default=32,
                     help="streams of the replicas workload (at most 32)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="replicas workload: keep the default tuning instead of running the "
+                         "library's autotuner per box size class")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket kernels with HIP events")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,

@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SDPD_ABI_VERSION 3
+#define SDPD_ABI_VERSION 4
 
 typedef enum {
     SDPD_OK = 0,
@@ -230,6 +230,22 @@ int sdpd_get_tuning(sdpd_ctx *ctx, sdpd_tuning *out);
 enum { SDPD_SWEEP_AUTO = 0, SDPD_SWEEP_ONE = 1, SDPD_SWEEP_PER_GROUP = 2 };
 int sdpd_set_sweep_mode(sdpd_ctx *ctx, int mode);
 int sdpd_sweep_mode(sdpd_ctx *ctx, int *in_use);
+
+/* Autotuner of the F/D sweep's execution-only parameters: the tasks per
+ * workgroup of each phase class (LDS capacities sized for them as the
+ * defaults are) and, when the mode is SDPD_SWEEP_AUTO, the layout.  It times
+ * `trials` sweeps (1..64) of each candidate on device-side scratch copies of
+ * state->p and state->eps, by coordinate descent from the current tuning
+ * (tasks x 1/2, 3/4, 3/2, 2 per class; a candidate must be 1 % faster), and
+ * keeps the fastest: the results of later calls do not depend on it.  The
+ * cells and masks must be current (sdpd_build_cells and sdpd_density, or a
+ * step, since the last change of the state); the state is not modified.
+ * Waits for the context's stream; allocates the scratch arrays (32 B per
+ * particle) for the duration of the call.  Writes the tuning in use to
+ * *chosen when it is not NULL.  Like sdpd_tune, invalidates captured
+ * batches.  SDPD_EINVAL for invalid arguments or stale cells; on a HIP
+ * error the previous tuning and mode are restored.                        */
+int sdpd_autotune(sdpd_ctx *ctx, const sdpd_state *state, int trials, sdpd_tuning *chosen);
 
 /* Batched replicas (many independent boxes advanced together).  Each box
  * is a context of its own (its parameters, replica index, stream) with its

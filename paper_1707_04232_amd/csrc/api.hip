@@ -1,6 +1,7 @@
 // C ABI of libsdpd: parameter checks, workspace, launch order, errors.
 #include <math.h>
 #include <algorithm>
+#include <cmath>
 #include <string.h>
 
 #include <new>
@@ -544,6 +545,147 @@ int sdpd_sweep_mode(sdpd_ctx *c, int *in_use)
     if (!c) return SDPD_EINVAL;
     if (in_use) *in_use = fd_one_launch(c) ? SDPD_SWEEP_ONE : SDPD_SWEEP_PER_GROUP;
     return c->sweep_mode;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Fastest of `trials` sweeps (ms) with the context's current tuning and
+// layout.  The schedule is in place; each trial starts from the momenta and
+// energies of s, copied into the scratch state w.
+int time_sweeps(sdpd_ctx *c, const sdpd_state *s, const sdpd_state *w, int trials,
+                hipEvent_t e0, hipEvent_t e1, double &best)
+{
+    const size_t n = (size_t)c->n;
+    const double dt_fd = c->prm.dt * c->prm.fd_every;
+    best = 1e300;
+    for (int t = 0; t < trials; ++t) {
+        int rc = check_hip(hipMemcpyAsync(w->p, s->p, sizeof(double) * 3 * n,
+                                          hipMemcpyDeviceToDevice, c->stream));
+        if (!rc) rc = check_hip(hipMemcpyAsync(w->eps, s->eps, sizeof(double) * n,
+                                               hipMemcpyDeviceToDevice, c->stream));
+        if (!rc) rc = launch_fill_u64(c, c->counters, 0ull, CNT_N);
+        if (!rc) rc = check_hip(hipEventRecord(e0, c->stream));
+        if (!rc) rc = fd_launch_sweep(c, w, dt_fd);
+        if (!rc) rc = check_hip(hipEventRecord(e1, c->stream));
+        if (!rc) rc = check_hip(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1));
+        if (rc) return rc;
+        best = std::min(best, (double)ms);
+    }
+    return SDPD_OK;
+}
+
+int autotune(sdpd_ctx *c, const sdpd_state *s, int trials, const sdpd_state *w, hipEvent_t e0,
+             hipEvent_t e1)
+{
+    int rc = launch_fill_u64(c, (unsigned long long *)c->dstep, 0ull, 1);
+    if (!rc) rc = fd_sweep_prepare(c, w, false);
+    if (rc) return rc;
+    const int mode0 = c->sweep_mode;
+    sdpd_tuning best = c->tuning;
+    double tbest;
+    if ((rc = time_sweeps(c, s, w, trials, e0, e1, tbest))) return rc;
+    // coordinate descent over the tasks per workgroup of each phase class,
+    // with the LDS capacities the defaults give that many tasks; a candidate
+    // must be 1 % faster to replace the current choice
+    static const double kFactor[4] = {0.5, 0.75, 1.5, 2.0};
+    for (int k = 0; k < 4; ++k) {
+        const int t0 = best.fd_tasks[k];
+        int tried[4] = {0, 0, 0, 0};
+        for (int f = 0; f < 4; ++f) {
+            const int t = std::min(std::max((int)std::lround(t0 * kFactor[f]), 1), FD_MAXTASKS);
+            bool seen = t == t0;
+            for (int q = 0; q < f; ++q) seen = seen || tried[q] == t;
+            tried[f] = t;
+            if (seen) continue;
+            sdpd_tuning u = best;
+            u.fd_tasks[k] = t;
+            fd_class_caps(c, k, t, u.fd_lds_particles[k], u.fd_lds_pairs[k]);
+            if (fd_check_tuning(c, &u)) continue;
+            c->tuning = u;
+            double tm;
+            if ((rc = fd_prepare_sweep(c)) || (rc = time_sweeps(c, s, w, trials, e0, e1, tm)))
+                return rc;
+            if (tm < 0.99 * tbest) {
+                best = u;
+                tbest = tm;
+            }
+        }
+    }
+    c->tuning = best;
+    if ((rc = fd_prepare_sweep(c))) return rc;
+    if (mode0 == SDPD_SWEEP_AUTO) {   // the layout too, unless the caller fixed it
+        int win = SDPD_SWEEP_AUTO;
+        for (int m = SDPD_SWEEP_ONE; m <= SDPD_SWEEP_PER_GROUP; ++m) {
+            c->sweep_mode = m;
+            double tm;
+            if ((rc = time_sweeps(c, s, w, trials, e0, e1, tm))) return rc;
+            if (tm < 0.99 * tbest) {
+                win = m;
+                tbest = tm;
+            }
+        }
+        c->sweep_mode = mode0;
+        if (win != SDPD_SWEEP_AUTO) {
+            // keep the automatic choice when it is the faster layout
+            c->sweep_mode = SDPD_SWEEP_AUTO;
+            const int autom = fd_one_launch(c) ? SDPD_SWEEP_ONE : SDPD_SWEEP_PER_GROUP;
+            c->sweep_mode = win == autom ? SDPD_SWEEP_AUTO : win;
+        }
+    }
+    return SDPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdpd_autotune(sdpd_ctx *c, const sdpd_state *s, int trials, sdpd_tuning *chosen)
+{
+    if (!c || !state_ok(c, s) || !c->cells_valid || !c->masks_valid || trials < 1 || trials > 64)
+        return SDPD_EINVAL;
+    if (c->prm.fd == SDPD_FD_NONE || c->n == 0) {
+        if (chosen) *chosen = c->tuning;
+        return SDPD_OK;
+    }
+    // scratch momenta and energies: the caller's state is not touched
+    sdpd_state w = *s;
+    double *wp = nullptr, *weps = nullptr;
+    int rc = dalloc(&wp, 3 * (size_t)c->n);
+    if (!rc) rc = dalloc(&weps, (size_t)c->n);
+    w.p = wp;
+    w.eps = weps;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc) rc = check_hip(hipEventCreate(&e0));
+    if (!rc) rc = check_hip(hipEventCreate(&e1));
+    const sdpd_tuning before = c->tuning;
+    const int mode_before = c->sweep_mode;
+    if (!rc) {
+        const int tt = c->timing;
+        c->timing = 0;   // the context's own event timer stays out of the trials
+        rc = check_hip(hipStreamSynchronize(c->stream));
+        if (!rc) {
+            ++c->tune_gen;   // graphs captured before keep the old launch size
+            rc = autotune(c, s, trials, &w, e0, e1);
+        }
+        c->timing = tt;
+        if (!rc) rc = take_error(c);
+        if (rc) {   // back to where the call started
+            c->tuning = before;
+            c->sweep_mode = mode_before;
+            (void)fd_prepare_sweep(c);
+        }
+    }
+    (void)hipStreamSynchronize(c->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (wp) (void)hipFree(wp);
+    if (weps) (void)hipFree(weps);
+    if (!rc && chosen) *chosen = c->tuning;
+    return rc;
 }
 
 }  // extern "C"

@@ -53,7 +53,6 @@
 
 namespace sdpd {
 
-constexpr int FD_MAXTASKS = 64;    // tasks per workgroup range
 constexpr int FD_NLVL = 64;        // levels of a task are 1..64
 constexpr int FD_EPL = 16;         // pair entries per lane held in registers
 constexpr int FD_PPL = 8;          // particle-list entries per lane per staging pass
@@ -633,24 +632,29 @@ int round_up(double x, int q)
 
 }  // namespace
 
-void fd_default_tuning(sdpd_ctx *c)
+void fd_class_caps(const sdpd_ctx *c, int k, int t, int &cp, int &ce)
 {
     const double s = c->ncell > 0 ? ((double)c->n / (double)c->ncell) / 17.5 : 1.0;
     const int lim = std::min(c->max_lds, 65536);
+    const double st = std::sqrt((double)t);
+    const double room = kAllow[k].room;
+    cp = round_up((t * kAllow[k].mp + 4.0 * st * kAllow[k].sp) * s * room, 16);
+    ce = round_up((t * kAllow[k].me + 4.0 * st * kAllow[k].se) * s * s * room, 64);
+    cp = std::min(std::max(cp, 128), 65535);
+    ce = std::max(ce, 64);
+    // shrink to the LDS limit, keeping the particle / pair proportion
+    while (fd_lds_bytes(cp, ce) > (size_t)lim && (cp > 128 || ce > 64)) {
+        cp = std::max(128, cp * 7 / 8);
+        ce = std::max(64, ce * 7 / 8);
+    }
+}
+
+void fd_default_tuning(sdpd_ctx *c)
+{
     for (int k = 0; k < 4; ++k) {
-        const int t = kDefaultTasks[k];
-        const double st = std::sqrt((double)t);
-        const double room = kAllow[k].room;
-        int cp = round_up((t * kAllow[k].mp + 4.0 * st * kAllow[k].sp) * s * room, 16);
-        int ce = round_up((t * kAllow[k].me + 4.0 * st * kAllow[k].se) * s * s * room, 64);
-        cp = std::min(std::max(cp, 128), 65535);
-        ce = std::max(ce, 64);
-        // shrink to the LDS limit, keeping the particle / pair proportion
-        while (fd_lds_bytes(cp, ce) > (size_t)lim && (cp > 128 || ce > 64)) {
-            cp = std::max(128, cp * 7 / 8);
-            ce = std::max(64, ce * 7 / 8);
-        }
-        c->tuning.fd_tasks[k] = t;
+        int cp, ce;
+        fd_class_caps(c, k, kDefaultTasks[k], cp, ce);
+        c->tuning.fd_tasks[k] = kDefaultTasks[k];
         c->tuning.fd_lds_particles[k] = cp;
         c->tuning.fd_lds_pairs[k] = ce;
     }
@@ -944,11 +948,10 @@ __global__ void k_pack_qrho(int64_t n, const double *__restrict__ q,
     qrho[i] = r;
 }
 
-// The step index of the draws is read from c->dstep on the device (set by
-// the caller, or advanced inside a captured graph).
-int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd, bool packed)
+// Schedule and packed records of a sweep (independent of the tuning), then
+// its launches.
+int fd_sweep_prepare(sdpd_ctx *c, const sdpd_state *s, bool packed)
 {
-    if (c->prm.fd == SDPD_FD_NONE || c->n == 0) return SDPD_OK;
     int rc = run_schedule(c);
     if (rc) return rc;
     if (!packed) {
@@ -959,7 +962,13 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd, bool packed)
         if ((rc = check_hip(hipGetLastError()))) return rc;
     }
     c->fd_swept = 1;
+    return SDPD_OK;
+}
+
+int fd_launch_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
+{
     if (!c->sweep_ok) return SDPD_EINVAL;
+    int rc;
     if (!fd_one_launch(c)) {
         for (const std::vector<int> &g : fd_groups())
             if ((rc = launch_phases(c, s, g.data(), (int)g.size(), dt_fd))) return rc;
@@ -974,6 +983,15 @@ int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd, bool packed)
                        c->epoch + c->ncell, c->epoch, c->counters);
     timer_end(c, TK_FD);
     return check_hip(hipGetLastError());
+}
+
+// The step index of the draws is read from c->dstep on the device (set by
+// the caller, or advanced inside a captured graph).
+int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd, bool packed)
+{
+    if (c->prm.fd == SDPD_FD_NONE || c->n == 0) return SDPD_OK;
+    const int rc = fd_sweep_prepare(c, s, packed);
+    return rc ? rc : fd_launch_sweep(c, s, dt_fd);
 }
 
 }  // namespace sdpd

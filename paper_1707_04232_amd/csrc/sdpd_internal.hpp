@@ -29,6 +29,7 @@ constexpr int NMASK = 14;
 constexpr int NNB = 27;
 constexpr int OWN_NB = 13;
 constexpr int MAX_CAP = 64;
+constexpr int FD_MAXTASKS = 64;    // tasks per workgroup range of the F/D sweep
 
 // Everything a kernel needs, by value.  Derived constants are computed once
 // on the host.
@@ -145,8 +146,14 @@ int run_forces_f32(sdpd_ctx *c, const sdpd_state *s, int half_kick);
 // packed: the (x, y, z, rho) records are already in place (a density pass
 // with pack_rho ran since the cells were built)
 int run_fd_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd, bool packed = false);
+// the two parts of run_fd_sweep: schedule (+ packing), then the launches
+int fd_sweep_prepare(sdpd_ctx *c, const sdpd_state *s, bool packed);
+int fd_launch_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd);
 int enqueue_step(sdpd_ctx *c, const sdpd_state *s, uint64_t step, bool set_step);
 void fd_default_tuning(sdpd_ctx *c);
+// LDS capacities (particles, pair entries) the defaults give phase class k
+// at t tasks per workgroup
+void fd_class_caps(const sdpd_ctx *c, int k, int t, int &cp, int &ce);
 int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t);
 int fd_prepare_sweep(sdpd_ctx *c);   // after any change of the tuning
 bool fd_one_launch(const sdpd_ctx *c);   // the sweep runs as one launch

@@ -24,7 +24,7 @@ EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
            "sdpd_copy_cell_start", "sdpd_density",
            "sdpd_forces", "sdpd_fd_metropolis", "sdpd_step", "sdpd_observe", "sdpd_sync",
            "sdpd_set_timing", "sdpd_timing", "sdpd_tune", "sdpd_get_tuning",
-           "sdpd_fd_schedule_size", "sdpd_set_sweep_mode", "sdpd_sweep_mode",
+           "sdpd_fd_schedule_size", "sdpd_set_sweep_mode", "sdpd_sweep_mode", "sdpd_autotune",
            "sdpd_batch_create", "sdpd_batch_run",
            "sdpd_batch_destroy", "sdpd_adjoint_forward", "sdpd_adjoint_backward",
            "sdpd_strerror",
@@ -96,6 +96,7 @@ def lib():
             "sdpd_set_timing": [vp, i32],
             "sdpd_timing": [vp, C.POINTER(C.c_double), C.POINTER(i64)],
             "sdpd_tune": [vp, C.POINTER(_Tuning)],
+            "sdpd_autotune": [vp, SP, i32, C.POINTER(_Tuning)],
             "sdpd_get_tuning": [vp, C.POINTER(_Tuning)],
             "sdpd_fd_schedule_size": [vp, C.POINTER(i64), C.POINTER(i64)],
             "sdpd_batch_create": [C.POINTER(vp), C.POINTER(_State), i32, C.POINTER(vp)],
@@ -284,6 +285,16 @@ class Context:
             for k, v in enumerate(vals or (0, 0, 0, 0)):
                 arr[k] = int(v)
         _check(lib().sdpd_tune(self._h, C.byref(t)), "sdpd_tune")
+
+    def autotune(self, s: "DeviceState", trials: int = 3) -> dict:
+        """Time candidate F/D tunings on scratch copies of s's momenta and
+        energies and keep the fastest (cells and masks must be current);
+        returns the tuning in use."""
+        t = _Tuning()
+        _check(lib().sdpd_autotune(self._h, C.byref(s.c()), int(trials), C.byref(t)),
+               "sdpd_autotune")
+        return {"fd_tasks": tuple(t.fd_tasks), "lds_particles": tuple(t.fd_lds_particles),
+                "lds_pairs": tuple(t.fd_lds_pairs)}
 
     def adjoint_forward(self, s: DeviceState, nsteps: int, checkpoint_every: int = 10):
         _check(lib().sdpd_adjoint_forward(self._h, C.byref(s.c()), int(nsteps),

@@ -187,6 +187,35 @@ def test_small_box_sweeps_per_group_by_default():
         assert ctx.sweep_mode() == (sdpd.SWEEP_ONE, sdpd.SWEEP_ONE)
 
 
+def test_autotune_keeps_state_and_results():
+    say("autotune")
+    sdpd = sd()
+    gp, op, S, R = _fd_case((24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0)
+    with sdpd.Context(gp) as ctx:   # default tuning
+        ctx.prepare(S)
+        ctx.fd_metropolis(S, step=3)
+        ref = S.to_numpy()
+    gp, op, S, R = _fd_case((24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0)
+    with sdpd.Context(gp) as ctx:
+        with pytest.raises(sdpd.SdpdError) as e:   # no cells yet
+            ctx.autotune(S)
+        assert e.value.rc == sdpd.EINVAL
+        ctx.prepare(S)
+        with pytest.raises(sdpd.SdpdError) as e:
+            ctx.autotune(S, trials=0)
+        assert e.value.rc == sdpd.EINVAL
+        before = S.to_numpy()
+        chosen = ctx.autotune(S, trials=2)
+        after = S.to_numpy()
+        for k in before:
+            assert np.array_equal(before[k], after[k]), k
+        assert ctx.get_tuning() == chosen
+        say("chosen", chosen, "mode", ctx.sweep_mode())
+        ctx.fd_metropolis(S, step=3)
+        got = S.to_numpy()
+    assert np.array_equal(got["p"], ref["p"]) and np.array_equal(got["eps"], ref["eps"])
+
+
 @pytest.mark.parametrize("sweep", ["one", "per_group"])
 def test_fd_sweep_tuning_does_not_change_results(sweep):
     say("fd sweep tuning invariance", sweep)
