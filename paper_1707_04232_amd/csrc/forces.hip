@@ -56,8 +56,12 @@ __global__ __launch_bounds__(256) void k_forces(DevParams P, const double *__res
     const double xi = qi.x, yi = qi.y, zi = qi.z, pii = qi.w;
     const double m2 = P.m * P.m;
     double fx = 0.0, fy = 0.0, fz = 0.0;
+    // the mask of the next neighbour cell is in flight while this one's
+    // partners are summed
+    uint64_t next = masks[i];
     for (int k = 0; k < 27; ++k) {
-        uint64_t mask = masks[(int64_t)k * n + i];
+        uint64_t mask = next;
+        if (k + 1 < 27) next = masks[(int64_t)(k + 1) * n + i];
         if (!mask) continue;
         const NbCell nb = neighbour_cell(P, cx, cy, cz, k);
         const uint32_t s = cell_start[nb.c];
