@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SDPD_ABI_VERSION 4
+#define SDPD_ABI_VERSION 5
 
 typedef enum {
     SDPD_OK = 0,
@@ -189,6 +189,9 @@ int sdpd_sync(sdpd_ctx *ctx);
  * 1 density, 2 F/D phase kernels, 3 forces + half kick, 4 observables,
  * 5 F/D scheduling pass.                                                   */
 int sdpd_set_timing(sdpd_ctx *ctx, int enable);
+/* The same for the classes whose bit is set in mask (bit k = class k); the
+ * other classes run without events.  SDPD_EINVAL for bits beyond class 5. */
+int sdpd_set_timing_mask(sdpd_ctx *ctx, uint32_t mask);
 int sdpd_timing(sdpd_ctx *ctx, double ms[6], int64_t launches[6]);
 
 /* Execution-only tuning of the F/D sweep (results do not change).  Index k

@@ -12,9 +12,12 @@ namespace sdpd {
 
 int check_hip(hipError_t e) { return e == hipSuccess ? SDPD_OK : SDPD_EHIP; }
 
+// c->timing: bit k set = the launches of timing class k are bracketed by
+// events
+
 void timer_begin(sdpd_ctx *c, int k)
 {
-    if (!c->timing) return;
+    if (!((c->timing >> k) & 1)) return;
     Timer &T = c->timer;
     if (T.used + 2 > T.pool.size()) {
         size_t old = T.pool.size();
@@ -28,8 +31,7 @@ void timer_begin(sdpd_ctx *c, int k)
 
 void timer_end(sdpd_ctx *c, int k)
 {
-    (void)k;
-    if (!c->timing) return;
+    if (!((c->timing >> k) & 1)) return;
     Timer &T = c->timer;
     (void)hipEventRecord(T.pool[T.used + 1], c->stream);
     T.used += 2;
@@ -465,9 +467,14 @@ int sdpd_sync(sdpd_ctx *c)
 
 int sdpd_set_timing(sdpd_ctx *c, int enable)
 {
-    if (!c) return SDPD_EINVAL;
+    return sdpd_set_timing_mask(c, enable ? (1u << TK_N) - 1u : 0u);
+}
+
+int sdpd_set_timing_mask(sdpd_ctx *c, uint32_t mask)
+{
+    if (!c || (mask >> TK_N) != 0u) return SDPD_EINVAL;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return SDPD_EHIP;
-    c->timing = enable != 0;
+    c->timing = (int)mask;
     c->timer.used = 0;
     return SDPD_OK;
 }

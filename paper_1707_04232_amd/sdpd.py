@@ -25,6 +25,7 @@ EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
            "sdpd_forces", "sdpd_fd_metropolis", "sdpd_step", "sdpd_observe", "sdpd_sync",
            "sdpd_set_timing", "sdpd_timing", "sdpd_tune", "sdpd_get_tuning",
            "sdpd_fd_schedule_size", "sdpd_set_sweep_mode", "sdpd_sweep_mode", "sdpd_autotune",
+           "sdpd_set_timing_mask",
            "sdpd_batch_create", "sdpd_batch_run",
            "sdpd_batch_destroy", "sdpd_adjoint_forward", "sdpd_adjoint_backward",
            "sdpd_strerror",
@@ -267,6 +268,13 @@ class Context:
 
     def set_timing(self, enable: bool):
         _check(lib().sdpd_set_timing(self._h, int(bool(enable))), "sdpd_set_timing")
+
+    def set_timing_classes(self, classes):
+        """Time only the named classes (names of TIMING_CLASSES)."""
+        mask = 0
+        for k in classes:
+            mask |= 1 << TIMING_CLASSES.index(k)
+        _check(lib().sdpd_set_timing_mask(self._h, C.c_uint32(mask)), "sdpd_set_timing_mask")
 
     def timing(self) -> dict:
         ms = (C.c_double * len(TIMING_CLASSES))()
