@@ -100,6 +100,109 @@ __global__ __launch_bounds__(256) void k_density(DevParams P, const double *__re
     }
 }
 
+// The same pass with four lanes per particle, for boxes too small to fill
+// the GPU with a thread per particle (the pass is then bound by the length
+// of one thread's candidate loop): lane q of a particle's group of four
+// takes candidates s + q, s + q + 4, ... of each neighbour cell and forms
+// m W(r), 0 out of range; the four lanes then add the four values in
+// candidate order.  Adding +0 leaves the sum unchanged, so rho is
+// bit-identical to k_density's.
+constexpr int64_t kQuadMaxParticles = 1 << 17;
+
+template <bool SHIFT>
+__device__ __forceinline__ uint64_t density_cell_quad(const DevParams &P,
+                                                      const double *__restrict__ q4, uint32_t s,
+                                                      uint32_t e, double xi, double yi, double zi,
+                                                      const NbCell &nb, double &acc, int q,
+                                                      int base)
+{
+    uint64_t mask = 0;
+    const uint32_t cnt = e - s;   // the same for the four lanes
+    for (uint32_t c0 = 0; c0 < cnt; c0 += 4) {
+        const uint32_t jj = c0 + (uint32_t)q;
+        double w = 0.0;
+        if (jj < cnt) {
+            const int64_t j = (int64_t)s + jj;
+            const double2 xy = *reinterpret_cast<const double2 *>(q4 + 4 * j);
+            double dx = xi - xy.x, dy = yi - xy.y, dz = zi - q4[4 * j + 2];
+            if (SHIFT) {
+                dx += nb.sx;
+                dy += nb.sy;
+                dz += nb.sz;
+            }
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < P.h2) {
+                w = P.m * kernel_w(P, fd_sqrt(fmax(r2, DBL_MIN)));
+                mask |= 1ull << jj;
+            }
+        }
+        const double w0 = __shfl(w, base), w1 = __shfl(w, base + 1);
+        const double w2 = __shfl(w, base + 2), w3 = __shfl(w, base + 3);
+        acc += w0;
+        acc += w1;
+        acc += w2;
+        acc += w3;
+    }
+    return mask;
+}
+
+__global__ __launch_bounds__(256) void k_density_quad(DevParams P, const double *__restrict__ q4,
+                                                      const uint32_t *__restrict__ cell_sorted,
+                                                      const uint32_t *__restrict__ cell_start,
+                                                      double *rho, double *eps, int update_eps,
+                                                      uint64_t *__restrict__ masks,
+                                                      uint32_t *err, double *rho_w)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = P.n;
+    const int64_t i = t >> 2;
+    const int q = (int)(threadIdx.x & 3u), base = (int)(threadIdx.x & 63u) & ~3;
+    // a group past the last particle runs the loops of the last one (its
+    // lanes must take part in the shuffles of their own group only) and
+    // stores nothing
+    const bool live = i < n;
+    const int64_t ii = live ? i : n - 1;
+    const uint32_t c = cell_sorted[ii];
+    const int cx = (int)(c % (uint32_t)P.nc[0]);
+    const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
+    const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
+    const double xi = q4[4 * ii], yi = q4[4 * ii + 1], zi = q4[4 * ii + 2];
+    double acc = 0.0;
+    const NbSteps steps(P, cx, cy, cz);
+    for (int k = 0; k < 27; ++k) {
+        const NbCell nb = steps.get(P, k);
+        const uint32_t s = cell_start[nb.c], e = cell_start[nb.c + 1];
+        if (e - s > (uint32_t)P.cap) {   // overflowing cell: reported, not visited
+            if (live && q == 0) {
+                atomicOr(err, ERR_CELLCAP);
+                masks[(int64_t)k * n + i] = 0ull;
+            }
+            continue;
+        }
+        const bool shifted = nb.sx != 0.0 || nb.sy != 0.0 || nb.sz != 0.0;
+        uint64_t mask = __any(shifted)
+                            ? density_cell_quad<true>(P, q4, s, e, xi, yi, zi, nb, acc, q, base)
+                            : density_cell_quad<false>(P, q4, s, e, xi, yi, zi, nb, acc, q, base);
+        uint32_t lo = (uint32_t)mask, hi = (uint32_t)(mask >> 32);
+        lo |= (uint32_t)__shfl_xor((int)lo, 1);
+        hi |= (uint32_t)__shfl_xor((int)hi, 1);
+        lo |= (uint32_t)__shfl_xor((int)lo, 2);
+        hi |= (uint32_t)__shfl_xor((int)hi, 2);
+        mask = ((uint64_t)hi << 32) | lo;
+        if (k == OWN_NB) mask &= ~(1ull << (ii - (int64_t)s));   // i itself is no partner
+        if (live && q == 0) masks[(int64_t)k * n + i] = mask;
+    }
+    if (!live || q != 0) return;
+    const double rho_old = rho[i];
+    rho[i] = acc;
+    if (rho_w) rho_w[4 * i + 3] = acc;
+    if (update_eps) {
+        double e_new = eps[i] * pow(acc / rho_old, P.eps_exp);
+        if (!(e_new > 0.0) || !isfinite(e_new)) atomicOr(err, ERR_NONFINITE);
+        eps[i] = e_new;
+    }
+}
+
 int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps, bool pack_rho)
 {
     if (c->n == 0) {
@@ -112,9 +215,14 @@ int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps, bool pack_rho)
         return rc;
     }
     timer_begin(c, TK_DENSITY);
-    hipLaunchKernelGGL(k_density, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, c->stream,
-                       c->dp, c->q4, c->cell_sorted, c->cell_start, s->rho, s->eps, update_eps,
-                       c->masks, c->err, pack_rho ? c->q4 : nullptr);
+    if (c->n <= kQuadMaxParticles)
+        hipLaunchKernelGGL(k_density_quad, dim3((unsigned)((4 * c->n + 255) / 256)), dim3(256), 0,
+                           c->stream, c->dp, c->q4, c->cell_sorted, c->cell_start, s->rho,
+                           s->eps, update_eps, c->masks, c->err, pack_rho ? c->q4 : nullptr);
+    else
+        hipLaunchKernelGGL(k_density, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0,
+                           c->stream, c->dp, c->q4, c->cell_sorted, c->cell_start, s->rho,
+                           s->eps, update_eps, c->masks, c->err, pack_rho ? c->q4 : nullptr);
     int rc = check_hip(hipGetLastError());
     timer_end(c, TK_DENSITY);
     if (!rc) c->masks_valid = 1;
