@@ -95,6 +95,7 @@ def lib():
             "sdpd_observe": [vp, SP, C.POINTER(_Stats)],
             "sdpd_sync": [vp],
             "sdpd_set_timing": [vp, i32],
+            "sdpd_set_timing_mask": [vp, C.c_uint32],
             "sdpd_timing": [vp, C.POINTER(C.c_double), C.POINTER(i64)],
             "sdpd_tune": [vp, C.POINTER(_Tuning)],
             "sdpd_autotune": [vp, SP, i32, C.POINTER(_Tuning)],

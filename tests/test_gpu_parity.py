@@ -187,6 +187,24 @@ def test_small_box_sweeps_per_group_by_default():
         assert ctx.sweep_mode() == (sdpd.SWEEP_ONE, sdpd.SWEEP_ONE)
 
 
+def test_timing_of_selected_classes():
+    say("timing mask")
+    sdpd = sd()
+    gp, op, S, R = _fd_case((24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0)
+    with sdpd.Context(gp) as ctx:
+        ctx.prepare(S)
+        ctx.set_timing_classes(["fd"])
+        ctx.step(S, 0, 2, stats=False)
+        tm = ctx.timing()
+        assert tm["fd"][1] > 0 and tm["fd"][0] > 0.0
+        for k, (ms, n) in tm.items():
+            if k != "fd":
+                assert n == 0 and ms == 0.0, k
+        # a bit beyond the six classes is refused
+        assert sdpd.lib().sdpd_set_timing_mask(ctx._h, 1 << 6) == sdpd.EINVAL
+        ctx.set_timing(False)
+
+
 def test_autotune_keeps_state_and_results():
     say("autotune")
     sdpd = sd()
