@@ -113,6 +113,10 @@ def lib():
                                           C.POINTER(C.c_int64)]),
             "so_fd_sweep": (C.c_int, [PP, _D, _D, _D, _D, _U32, _U32, C.c_uint64,
                                       C.c_double, SP, C.c_void_p, C.c_int64]),
+            "so_fd_sweep_flip": (C.c_int, [PP, _D, _D, _D, _D, _U32, _U32, C.c_uint64,
+                                           C.c_double, SP, C.c_void_p, C.c_int64,
+                                           C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                           C.c_int64]),
             "so_observe": (C.c_int, [PP, _D, _D, SP]),
             "so_kick": (C.c_int, [PP, _D, _D, C.c_double]),
             "so_drift": (C.c_int, [PP, _D, _D, C.c_double]),
@@ -308,18 +312,30 @@ def fd_pair_list(P, S: State):
     return out
 
 
-def fd_sweep(P, S: State, step, dt_fd=None, log=False):
-    """One F/D sweep in place.  Returns (rc, stats, pair log or None)."""
+def fd_sweep(P, S: State, step, dt_fd=None, log=False, flip=()):
+    """One F/D sweep in place.  Returns (rc, stats, pair log or None).
+    flip: {position in sweep order: kind}, kind bit 0 inverts the outcome of
+    the energy bound and bit 1 that of the Metropolis test of that pair (a
+    test control for decisions inside the rounding margin)."""
     st = _Stats()
     rec = None
     cap = 0
     if log:
         cap = len(fd_pair_list(P, S))
         rec = np.zeros(cap, PAIRREC_DTYPE)
-    rc = lib().so_fd_sweep(C.byref(P.c()), _d(S.q), _d(S.p), _d(S.eps), _d(S.rho),
-                           _u(S.id), _u(S.cell_start), step,
-                           P.dt * P.fd_every if dt_fd is None else dt_fd, C.byref(st),
-                           None if rec is None else rec.ctypes.data_as(C.c_void_p), cap)
+    dt = P.dt * P.fd_every if dt_fd is None else dt_fd
+    out = None if rec is None else rec.ctypes.data_as(C.c_void_p)
+    if len(flip):
+        pos = sorted(int(k) for k in flip)
+        fl = np.ascontiguousarray(pos, np.int64)
+        kind = np.ascontiguousarray([int(flip[k]) for k in pos], np.int32)
+        rc = lib().so_fd_sweep_flip(C.byref(P.c()), _d(S.q), _d(S.p), _d(S.eps), _d(S.rho),
+                                    _u(S.id), _u(S.cell_start), step, dt, C.byref(st), out,
+                                    cap, fl.ctypes.data_as(C.POINTER(C.c_int64)),
+                                    kind.ctypes.data_as(C.POINTER(C.c_int32)), len(fl))
+    else:
+        rc = lib().so_fd_sweep(C.byref(P.c()), _d(S.q), _d(S.p), _d(S.eps), _d(S.rho),
+                               _u(S.id), _u(S.cell_start), step, dt, C.byref(st), out, cap)
     return rc, stats_dict(st), rec
 
 

@@ -500,10 +500,15 @@ double so_fd_log_ratio(const so_params *P, double F, double rho_i, double rho_j,
 #define SO_MARGIN_BOUND 1e-12
 
 /* One EMS / AMS / SSA update of pair (i, j), Sec. 3.3.2 (the four steps of
- * the exact Metropolis scheme) and Sec. 3.3.3.  Returns the decision.       */
+ * the exact Metropolis scheme) and Sec. 3.3.3.  Returns the decision.
+ * flip is a test control (reading A16): bit 0 inverts the outcome of the
+ * energy bound, bit 1 the outcome of the Metropolis test, so that a check
+ * can follow the other side's outcome of a test that lies inside the
+ * rounding margin; the tests still run in their order (an inverted bound
+ * rejection goes on to the ratio).  The arithmetic is the same either way. */
 static int fd_pair(const so_params *P, const double *q, double *p, double *eps,
                    const double *rho, const uint32_t *id, int64_t i, int64_t j,
-                   uint64_t step, double dt, so_stats *st, so_pairrec *rec)
+                   uint64_t step, double dt, so_stats *st, so_pairrec *rec, int flip)
 {
     int64_t n = P->n;
     if (id[i] > id[j]) { int64_t t = i; i = j; j = t; }   /* A11 */
@@ -538,7 +543,7 @@ static int fd_pair(const so_params *P, const double *q, double *p, double *eps,
     st->proposed += 1;
     if (P->fd_mode == SO_FD_SSA) {
         if (!(eps_new[0] > 0.0 && eps_new[1] > 0.0)) st->negeps += 1;
-    } else if (!(emin > delta)) {                      /* eq. (energy-bound) */
+    } else if ((emin > delta) == ((flip & 1) != 0)) {   /* eq. (energy-bound) */
         decision = 1;
     } else if (P->fd_mode == SO_FD_EMS) {
         double vn2[3], en2[2];
@@ -546,7 +551,7 @@ static int fd_pair(const so_params *P, const double *q, double *p, double *eps,
                                    vn2, en2);
         amlu = a - log(U);
         if (fabs(amlu) <= SO_MARGIN_RATIO) st->marginal += 1;
-        if (U > exp(a)) decision = 2;                  /* reject iff U > A */
+        if ((U > exp(a)) != ((flip & 2) != 0)) decision = 2;   /* reject iff U > A */
     }
     if (P->fd_mode != SO_FD_SSA && fabs(gap) <= SO_MARGIN_BOUND * fmax(fabs(emin), fabs(delta)))
         st->marginal += 1;
@@ -651,27 +656,56 @@ int so_fd_pair_list(const so_params *P, const double *q, const uint32_t *cell_st
     return cnt > cap ? SO_EINVAL : SO_OK;
 }
 
-/* One fluctuation/dissipation sweep: every active pair once, in key order. */
-int so_fd_sweep(const so_params *P, const double *q, double *p, double *eps,
-                const double *rho, const uint32_t *id, const uint32_t *cell_start,
-                uint64_t step, double dt_fd, so_stats *st,
-                so_pairrec *log, int64_t log_cap)
+/* One fluctuation/dissipation sweep: every active pair once, in key order.
+ * The pairs at positions flip_pos[0..nflip) of that order (ascending; may be
+ * NULL) take the test inversions flip_kind[] (see fd_pair).                */
+static int fd_sweep(const so_params *P, const double *q, double *p, double *eps,
+                    const double *rho, const uint32_t *id, const uint32_t *cell_start,
+                    uint64_t step, double dt_fd, so_stats *st, so_pairrec *log,
+                    int64_t log_cap, const int64_t *flip_pos, const int32_t *flip_kind,
+                    int64_t nflip)
 {
     if (P->fd_mode == SO_FD_NONE) return SO_OK;
     pairkey *list = NULL;
     int64_t cnt = 0;
     int rc = build_pairs(P, q, cell_start, &list, &cnt);
     if (rc) return rc;
+    int64_t next = 0;
     for (int64_t k = 0; k < cnt; ++k) {
         so_pairrec *rec = (log && k < log_cap) ? &log[k] : NULL;
         if (rec) {
             rec->phase = list[k].phase;
             rec->round = list[k].round;
         }
-        fd_pair(P, q, p, eps, rho, id, list[k].i, list[k].j, step, dt_fd, st, rec);
+        int f = 0;
+        while (next < nflip && flip_pos[next] < k) ++next;
+        if (next < nflip && flip_pos[next] == k) f = flip_kind[next];
+        fd_pair(P, q, p, eps, rho, id, list[k].i, list[k].j, step, dt_fd, st, rec, f);
     }
     free(list);
     return st->negeps ? SO_ENEGEPS : SO_OK;
+}
+
+int so_fd_sweep(const so_params *P, const double *q, double *p, double *eps,
+                const double *rho, const uint32_t *id, const uint32_t *cell_start,
+                uint64_t step, double dt_fd, so_stats *st,
+                so_pairrec *log, int64_t log_cap)
+{
+    return fd_sweep(P, q, p, eps, rho, id, cell_start, step, dt_fd, st, log, log_cap, NULL, NULL,
+                    0);
+}
+
+int so_fd_sweep_flip(const so_params *P, const double *q, double *p, double *eps,
+                     const double *rho, const uint32_t *id, const uint32_t *cell_start,
+                     uint64_t step, double dt_fd, so_stats *st,
+                     so_pairrec *log, int64_t log_cap, const int64_t *flip_pos,
+                     const int32_t *flip_kind, int64_t nflip)
+{
+    for (int64_t k = 0; k < nflip; ++k)
+        if ((k > 0 && flip_pos[k] <= flip_pos[k - 1]) || flip_kind[k] < 0 || flip_kind[k] > 3)
+            return SO_EINVAL;
+    return fd_sweep(P, q, p, eps, rho, id, cell_start, step, dt_fd, st, log, log_cap, flip_pos,
+                    flip_kind, nflip);
 }
 
 /* ======================================================================= */

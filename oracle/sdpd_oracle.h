@@ -101,6 +101,16 @@ int so_fd_sweep(const so_params *P, const double *q, double *p, double *eps,
                 const double *rho, const uint32_t *id, const uint32_t *cell_start,
                 uint64_t step, double dt_fd, so_stats *st,
                 so_pairrec *log, int64_t log_cap);
+/* the same sweep where, for the pairs at positions flip_pos[0..nflip)
+ * (ascending, in sweep order), the outcome of the energy bound (bit 0 of
+ * flip_kind) and/or of the Metropolis test (bit 1) is inverted: a test
+ * control for decisions inside the rounding margin (reading A16).
+ * SO_EINVAL if flip_pos is not strictly ascending or a kind is not 0..3.   */
+int so_fd_sweep_flip(const so_params *P, const double *q, double *p, double *eps,
+                     const double *rho, const uint32_t *id, const uint32_t *cell_start,
+                     uint64_t step, double dt_fd, so_stats *st,
+                     so_pairrec *log, int64_t log_cap, const int64_t *flip_pos,
+                     const int32_t *flip_kind, int64_t nflip);
 
 /* --- full step and observables ----------------------------------------- */
 int so_observe(const so_params *P, const double *p, const double *eps, so_stats *st);

@@ -4,10 +4,14 @@ spread over three streams and advanced by one captured HIP graph.  Every
 replay must give exactly (bit for bit) what the eager sdpd_step gives on a
 second, independent set of contexts; the replays are interleaved with eager
 work on the same contexts (observables, synchronisation) and each replay is
-checked."""
+checked.  Three boxes with different replica indices and a Philox key whose
+both halves are non-zero are also stepped through the batch and compared
+with the oracle's so_step, box by box."""
 import numpy as np
 import pytest
 
+import oracle as O
+import parity_util as PU
 from paper_1707_04232_amd.workload import lattice_state, replica_set
 
 pytestmark = pytest.mark.gpu
@@ -70,8 +74,9 @@ def test_batch_graph_matches_eager_steps(fd_every):
 
 
 _PER_STREAM_CHILD = r"""
-import sys
+import os, sys
 sys.path.insert(0, sys.argv[1])
+sys.path.insert(0, os.path.join(sys.argv[1], "tests"))
 import numpy as np, torch
 from paper_1707_04232_amd import sdpd
 from tests.test_gpu_batch import _boxes
@@ -130,4 +135,102 @@ def test_batch_refuses_a_retuned_context():
             B.run(1, 1)
     for c, _ in bat:
         c.sync()
+        c.close()
+
+
+SEED_HI = 0x1234_5678_9ABC_DEF0
+ORACLE_BOXES = [   # side, T, Cv, replica
+    (10, 0.1, 1.5, 0),
+    (11, 1.0, 10.0, 3),
+    (12, 0.5, 3.0, 255),
+]
+
+
+def _oracle_boxes(nsteps):
+    """The oracle's trajectories of ORACLE_BOXES, stage by stage with the
+    sweep logs; returns (initial states, final states, logs per box)."""
+    init, fin, logs = [], [], []
+    for side, T, Cv, rep in ORACLE_BOXES:
+        q, p, eps, ids = lattice_state(side, Cv=Cv, T=T, seed=rep)
+        P = O.OracleParams(n=len(eps), box=float(side), Cv=Cv, seed=SEED_HI, replica=rep)
+        R = O.State.from_arrays(q, p, eps, ids)
+        init.append((q, p, eps, ids, P))
+        O.prepare(P, R)
+        lg = []
+        for k in range(nsteps):
+            eps_before = R.eps.copy()
+            rc, st, log = PU.oracle_step_logged(P, R, k)
+            assert rc == 0
+            lg.append((st, log, eps_before))
+        fin.append(R)
+        logs.append(lg)
+    return init, fin, logs
+
+
+def _batch_of(init, streams):
+    import torch
+    from paper_1707_04232_amd import sdpd
+    out = []
+    for b, (q, p, eps, ids, P) in enumerate(init):
+        prm = sdpd.SdpdParams(n=len(eps), box=P.box, Cv=P.Cv, seed=SEED_HI, replica=P.replica)
+        S = sdpd.DeviceState.from_numpy(q, p, eps, ids)
+        with torch.cuda.stream(streams[b % len(streams)]):
+            ctx = sdpd.Context(prm)
+        ctx.prepare(S)
+        out.append((ctx, S))
+    torch.cuda.synchronize()
+    return out
+
+
+def test_batch_boxes_match_oracle():
+    """Each box of a captured batch (replica 0, 3, 255; a 64-bit key) after
+    four replayed steps against the oracle at 1e-10.  The GPU's marginal
+    decisions are a subset of the oracle pairs inside the widened window of
+    parity_util; when no step of any box holds such a pair, the whole states
+    are compared; otherwise the boxes are replayed one step at a time under
+    the protocol of parity_util."""
+    import torch
+    from paper_1707_04232_amd import sdpd
+    nsteps = 4
+    say("batch boxes vs oracle", ORACLE_BOXES)
+    init, fin, logs = _oracle_boxes(nsteps)
+    nseed = sum(int(PU.seeds(lg, O.FD_EMS, float(np.abs(eb).max())).sum())
+                for box in logs for (_, lg, eb) in box)
+    say(f"oracle pairs inside the marginal window: {nseed}")
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    bat = _batch_of(init, streams)
+    with sdpd.Batch([c for c, _ in bat], [s for _, s in bat]) as B:
+        if nseed == 0:
+            B.run(0, nsteps)
+            for (c, S), R, lg in zip(bat, fin, logs):
+                c.sync()
+                g = S.to_numpy()
+                assert np.array_equal(g["id"], R.id)
+                for k in ("q", "p", "eps", "rho", "f"):
+                    ref = getattr(R, k)
+                    e = np.abs(g[k] - ref).max() / np.abs(ref).max()
+                    assert e <= 1e-10, f"{k}: {e:.2e}"
+                last = c.observe(S)   # counters of the last sweep
+                ost = lg[-1][0]
+                for k in ("proposed", "rej_energy", "rej_ratio"):
+                    assert last[k] == ost[k], k
+                assert abs(last["E"] - ost["E"]) <= 1e-10 * abs(ost["E"])
+        else:
+            Rs = []
+            for q, p, eps, ids, P in init:
+                R = O.State.from_arrays(q, p, eps, ids)
+                O.prepare(P, R)
+                Rs.append(R)
+            for k in range(nsteps):
+                B.run(k, 1)
+                for b, (c, S) in enumerate(bat):
+                    c.sync()
+                    # counters of the step just replayed; the batch reports no
+                    # per-step marginal count, so the oracle's seeds decide
+                    gst = dict(c.observe(S), marginal=None)
+                    Rs[b], _, resync = PU.step_and_compare(init[b][4], Rs[b], k, S.to_numpy(),
+                                                           gst, 1e-10, say)
+                    if resync:
+                        PU.load_state(S, Rs[b])
+    for c, _ in bat:
         c.close()

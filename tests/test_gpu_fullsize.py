@@ -8,13 +8,17 @@ then take one more full step (cells, density with the constant-entropy
 energy update, the Metropolized F/D sweep over ~4e7 pairs, forces and the
 two half kicks).  Every element of the resulting state is compared (1e-10
 relative), the particle order must be identical and the accept/reject
-counters equal unless a decision fell inside the rounding margin."""
+counters equal.  If a decision fell inside the rounding margin on either
+side, the oracle step is re-run stage by stage with its pair log and the
+protocol of parity_util applies (re-sync of the marginal outcomes, or the
+taint rule): the state is still compared element by element."""
 import time
 
 import numpy as np
 import pytest
 
 import oracle as O
+import parity_util as PU
 from paper_1707_04232_amd.workload import WORKLOADS, workload_state
 
 pytestmark = pytest.mark.gpu
@@ -55,26 +59,16 @@ def test_full_size_step_parity():
         g = S.to_numpy()
     say("gpu done; oracle step on the host")
     R = O.State.from_arrays(h["q"], h["p"], h["eps"], h["id"], rho=h["rho"], f=h["f"])
+    R0 = R.copy()
     t0 = time.perf_counter()
     rc, ost = O.step(op, R, 3, 1)
     say(f"oracle step {time.perf_counter() - t0:.1f} s")
     ost = ost[0]
     assert rc == 0
-    assert np.array_equal(g["id"], R.id), "particle order differs"
+    assert gst["proposed"] > 35 * w.n   # ~40 active pairs per particle
+    R, ost, _ = PU.step_and_compare(op, R0, 3, g, gst, 1e-10, say, ost=ost, R=R)
     for k in ("q", "rho"):   # before the sweep in the step
         assert rel(g[k], getattr(R, k)) <= 1e-12, k
-    assert gst["proposed"] == ost["proposed"]
-    assert gst["proposed"] > 35 * w.n   # ~40 active pairs per particle
-    marginal = gst["marginal"] + ost["marginal"]
-    if marginal == 0:
-        assert (gst["rej_energy"], gst["rej_ratio"]) == (ost["rej_energy"], ost["rej_ratio"])
-        for k in ("p", "eps", "f"):
-            e = rel(g[k], getattr(R, k))
-            assert e <= 1e-10, f"{k}: relative error {e:.3e}"
-        assert abs(gst["E"] - ost["E"]) <= 1e-10 * abs(ost["E"])
-    else:   # a decision inside the rounding margin may go either way
-        d = abs(gst["rej_energy"] + gst["rej_ratio"] - ost["rej_energy"] - ost["rej_ratio"])
-        assert d <= marginal
 
 
 def test_full_size_ssa_reports_negative_energies():

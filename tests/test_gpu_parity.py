@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import parity_util as PU
 from paper_1707_04232_amd.workload import lattice_state, shuffled, uniform_state
 
 pytestmark = pytest.mark.gpu
@@ -126,35 +127,44 @@ def test_density_constant_entropy_update():
     compare_state(S.to_numpy(), R, 1e-12, keys=("rho", "eps"))
 
 
+SEED_HI = 0x1234_5678_9ABC_DEF0   # both 32-bit halves of the Philox key non-zero
+
 FD_CASES = [
-    # name, dims, Cv, T, dt, fd mode, kernel, zeta
-    ("ems_cv10", 10, 10.0, 1.0, 0.005, 0, 0, 0.0),
-    ("ems_cv1.5_T0.1", 10, 1.5, 0.1, 0.005, 0, 0, 0.0),
-    ("ems_cv1.5_dt1", 10, 1.5, 0.1, 1.0, 0, 0, 0.0),
-    ("ems_cubic_zeta", 10, 3.0, 0.5, 0.3, 0, 1, 0.4),
-    ("ams_cv1.5_dt1", 10, 1.5, 0.1, 1.0, 1, 0, 0.0),
-    ("ssa_cv10", 10, 10.0, 1.0, 0.005, 2, 0, 0.0),
-    ("ems_24x20x16", (24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0),
-    ("ems_32", 32, 1.5, 0.1, 0.005, 0, 0, 0.0),
+    # name, dims, Cv, T, dt, fd mode, kernel, zeta, seed, replica
+    ("ems_cv10", 10, 10.0, 1.0, 0.005, 0, 0, 0.0, 0, 0),
+    ("ems_cv1.5_T0.1", 10, 1.5, 0.1, 0.005, 0, 0, 0.0, 0, 0),
+    ("ems_cv1.5_dt1", 10, 1.5, 0.1, 1.0, 0, 0, 0.0, 0, 0),
+    ("ems_cubic_zeta", 10, 3.0, 0.5, 0.3, 0, 1, 0.4, 0, 0),
+    ("ams_cv1.5_dt1", 10, 1.5, 0.1, 1.0, 1, 0, 0.0, 0, 0),
+    ("ssa_cv10", 10, 10.0, 1.0, 0.005, 2, 0, 0.0, 0, 0),
+    ("ems_24x20x16", (24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0, 0, 0),
+    ("ems_32", 32, 1.5, 0.1, 0.005, 0, 0, 0.0, 0, 0),
     # large moves: the cubic brackets of the Metropolis test often fail and
     # the logarithms are evaluated; Cv < kB makes the entropy factor negative
-    ("ems_cv1.5_dt5", 10, 1.5, 1.0, 5.0, 0, 0, 0.0),
-    ("ems_cv0.8_dt0.5", 10, 0.8, 1.0, 0.5, 0, 0, 0.0),
+    ("ems_cv1.5_dt5", 10, 1.5, 1.0, 5.0, 0, 0, 0.0, 0, 0),
+    ("ems_cv0.8_dt0.5", 10, 0.8, 1.0, 0.5, 0, 0, 0.0, 0, 0),
+    # the whole Philox key and the replica word of the counter (Sec. 3.2 G,
+    # Sec. 3.3.2 U): a swapped key half or a wrong replica word changes every draw
+    ("ems_seedhi_rep3", 10, 1.5, 0.1, 0.5, 0, 0, 0.0, SEED_HI, 3),
+    ("ems_seedhi_rep255", (24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0, SEED_HI, 255),
+    ("ssa_seedhi_rep255", 10, 10.0, 1.0, 0.005, 2, 0, 0.0, SEED_HI, 255),
+    ("ems_seed2^32_rep1", 10, 3.0, 0.5, 1.0, 0, 1, 0.4, 1 << 32, 1),
 ]
 
 
-def _fd_case(dims, Cv, T, dt, mode, kernel, zeta, jitter=0.05):
+def _fd_case(dims, Cv, T, dt, mode, kernel, zeta, jitter=0.05, seed=0, replica=0):
     q, p, eps, ids = lattice_state(dims, Cv=Cv, T=T, jitter=jitter)
     box = tuple(float(d) for d in ((dims,) * 3 if np.ndim(dims) == 0 else dims))
-    return both(q, p, eps, ids, box, Cv=Cv, dt=dt, fd=mode, kernel=kernel, zeta=zeta)
+    return both(q, p, eps, ids, box, Cv=Cv, dt=dt, fd=mode, kernel=kernel, zeta=zeta,
+                seed=seed, replica=replica)
 
 
 @pytest.mark.parametrize("sweep", ["one", "per_group"])
-@pytest.mark.parametrize("name,dims,Cv,T,dt,mode,kernel,zeta", FD_CASES,
+@pytest.mark.parametrize("name,dims,Cv,T,dt,mode,kernel,zeta,seed,replica", FD_CASES,
                          ids=[c[0] for c in FD_CASES])
-def test_fd_sweep_parity(name, dims, Cv, T, dt, mode, kernel, zeta, sweep):
-    say("fd sweep", name, sweep)
-    gp, op, S, R = _fd_case(dims, Cv, T, dt, mode, kernel, zeta)
+def test_fd_sweep_parity(name, dims, Cv, T, dt, mode, kernel, zeta, seed, replica, sweep):
+    say("fd sweep", name, sweep, f"seed {seed:#x} replica {replica}")
+    gp, op, S, R = _fd_case(dims, Cv, T, dt, mode, kernel, zeta, seed=seed, replica=replica)
     sdpd = sd()
     with sdpd.Context(gp) as ctx:
         ctx.set_sweep_mode(sdpd.SWEEP_ONE if sweep == "one" else sdpd.SWEEP_PER_GROUP)
@@ -162,12 +172,7 @@ def test_fd_sweep_parity(name, dims, Cv, T, dt, mode, kernel, zeta, sweep):
         ctx.prepare(S)
         gst = ctx.fd_metropolis(S, step=7)
     O.prepare(op, R)
-    rc, ost, _ = O.fd_sweep(op, R, 7)
-    assert rc == 0
-    assert gst["proposed"] == ost["proposed"]
-    if gst["marginal"] == 0 and ost["marginal"] == 0:
-        assert (gst["rej_energy"], gst["rej_ratio"]) == (ost["rej_energy"], ost["rej_ratio"])
-        compare_state(S.to_numpy(), R, 1e-10, keys=("p", "eps"))
+    PU.sweep_and_compare(op, R, 7, S.to_numpy(), gst, 1e-10, say)
     if mode == 0 and dt >= 0.3:
         assert gst["rej_energy"] + gst["rej_ratio"] > 0
 
@@ -275,8 +280,24 @@ def test_fd_sweep_tuning_does_not_change_results(sweep):
         assert ctx.get_tuning() == before
 
 
-def _run_steps(dims, nsteps, **kw):
-    q, p, eps, ids = lattice_state(dims, Cv=kw.get("Cv", 10.0), T=kw.pop("T", 1.0))
+@pytest.mark.parametrize("name,dims,nsteps,kw", [
+    ("c1_ems_100", 10, 100, dict(Cv=10.0, T=1.0)),
+    ("cv1.5_T0.1_50", 10, 50, dict(Cv=1.5, T=0.1)),
+    ("mts_theta5", 10, 30, dict(Cv=1.5, T=0.1, fd_every=5)),
+    ("mts_theta10", 10, 40, dict(Cv=1.5, T=0.1, fd_every=10)),
+    ("ams_cubic", 12, 20, dict(Cv=2.0, T=0.2, fd=1, kernel=1)),
+    ("seedhi_rep3", 10, 30, dict(Cv=1.5, T=0.1, seed=SEED_HI, replica=3)),
+    ("seedhi_rep255_theta2", 10, 30, dict(Cv=10.0, T=1.0, seed=SEED_HI, replica=255,
+                                          fd_every=2)),
+])
+def test_step_trajectory_parity(name, dims, nsteps, kw):
+    """The whole trajectory in one sdpd_step call (the benchmark's path) and
+    one oracle so_step call; if a decision fell inside the rounding margin on
+    either side, both sides are re-run from the start one step at a time with
+    the taint comparison and a re-sync after each marginal step."""
+    say("steps", name)
+    T = kw.pop("T", 1.0)
+    q, p, eps, ids = lattice_state(dims, Cv=kw.get("Cv", 10.0), T=T)
     box = tuple(float(d) for d in ((dims,) * 3 if np.ndim(dims) == 0 else dims))
     gp, op, S, R = both(q, p, eps, ids, box, **kw)
     with sd().Context(gp) as ctx:
@@ -284,27 +305,25 @@ def _run_steps(dims, nsteps, **kw):
         gst = ctx.step(S, 0, nsteps)
     O.prepare(op, R)
     rc, ost = O.step(op, R, 0, nsteps)
-    return S.to_numpy(), R, gst, ost, rc
-
-
-@pytest.mark.parametrize("name,dims,nsteps,kw", [
-    ("c1_ems_100", 10, 100, dict(Cv=10.0, T=1.0)),
-    ("cv1.5_T0.1_50", 10, 50, dict(Cv=1.5, T=0.1)),
-    ("mts_theta5", 10, 30, dict(Cv=1.5, T=0.1, fd_every=5)),
-    ("ams_cubic", 12, 20, dict(Cv=2.0, T=0.2, fd=1, kernel=1)),
-])
-def test_step_trajectory_parity(name, dims, nsteps, kw):
-    say("steps", name)
-    g, R, gst, ost, rc = _run_steps(dims, nsteps, **kw)
     assert rc == 0
     marginal = sum(s["marginal"] for s in gst) + sum(s["marginal"] for s in ost)
-    assert marginal == 0, "a decision fell inside the rounding margin: re-run with another seed"
-    for a, b in zip(gst, ost):
-        assert (a["proposed"], a["rej_energy"], a["rej_ratio"]) == \
-               (b["proposed"], b["rej_energy"], b["rej_ratio"])
-        assert abs(a["E"] - b["E"]) <= 1e-10 * abs(b["E"])
-    compare_state(g, R, 1e-10)
-    # momentum stays zero, energy stays close
+    say(f"marginal decisions over {nsteps} steps: gpu {sum(s['marginal'] for s in gst)}, "
+        f"oracle {sum(s['marginal'] for s in ost)}")
+    if marginal == 0:
+        for a, b in zip(gst, ost):
+            assert (a["proposed"], a["rej_energy"], a["rej_ratio"]) == \
+                   (b["proposed"], b["rej_energy"], b["rej_ratio"])
+            assert abs(a["E"] - b["E"]) <= 1e-10 * abs(b["E"])
+        compare_state(S.to_numpy(), R, 1e-10)
+    else:
+        gp, op, S, R = both(q, p, eps, ids, box, **kw)
+        with sd().Context(gp) as ctx:
+            ctx.prepare(S)
+            O.prepare(op, R)
+            R, n = PU.stepwise_trajectory(ctx, S, op, R, 0, nsteps, 1e-10, say)
+            say(f"step by step: {n} steps re-synced by the taint rule")
+            gst = [ctx.observe(S)]
+    # momentum stays zero
     assert max(abs(x) for x in gst[-1]["P"]) < 1e-9
 
 
@@ -376,7 +395,4 @@ def test_full_cell_at_capacity():
     O.prepare(op, R)
     assert np.diff(R.cell_start.astype(np.int64)).max() == 64
     assert np.array_equal(cs, R.cell_start)
-    rc, ost, _ = O.fd_sweep(op, R, 1)
-    assert gst["proposed"] == ost["proposed"]
-    if gst["marginal"] == 0 and ost["marginal"] == 0:
-        compare_state(S.to_numpy(), R, 1e-10, keys=("p", "eps"))
+    PU.sweep_and_compare(op, R, 1, S.to_numpy(), gst, 1e-10, say)
