@@ -62,8 +62,11 @@ typedef enum { SDPD_FP64 = 0, SDPD_MIXED = 1 } sdpd_prec;
 
 /* Physical and numerical parameters.  Ideal-gas entropy closure
  *   S(eps, rho) = Cv ln eps - A kB ln(rho / rho0)          (eq. pg-eos)
- * so T = eps/Cv, P = A kB rho eps / (m Cv), C = Cv (Sec. 2.1.2).
- * Requirements: n >= 0; m, h, kB, Cv, A, rho0, dt > 0; Cv > kB/2 (so that
+ * so T = eps/Cv, P = A kB rho eps / (m Cv), C = Cv (Sec. 2.1.2).  A = 0
+ * selects the default A = Cv / (3 kB) (the paper's ideal-gas entropy of
+ * Sec. 4 with kB restored in its density term).
+ * Requirements: n >= 0; m, h, kB, Cv, rho0, dt > 0; A > 0 or A == 0 (the
+ * default); Cv > kB/2 (so that
  * d_ij < 1); eta > 0 and 0 <= zeta < 5 eta / 3 (both kappas positive);
  * box[k] / ncell[k] >= h with ncell[k] even and >= 4 (ncell[k] = 0 picks the
  * largest even integer <= box[k]/h); 1 <= cell_cap <= 64; fd_every >= 1.   */
@@ -71,7 +74,7 @@ typedef struct {
     int64_t n;            /* number of particles                            */
     double box[3];        /* periodic box lengths                           */
     double m, h, kB;      /* particle mass, smoothing length, Boltzmann     */
-    double Cv, A, rho0;   /* heat capacity, EOS density exponent, ref. density */
+    double Cv, A, rho0;   /* heat capacity, EOS coefficient (0 = Cv/(3 kB)), ref. density */
     double eta, zeta;     /* shear and bulk viscosity                       */
     double dt;            /* time step                                      */
     int32_t fd_every;     /* theta: F/D every theta steps with theta*dt (Sec. 4.2) */

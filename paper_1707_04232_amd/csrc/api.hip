@@ -52,14 +52,23 @@ static int grid_axis(double box, double h, int req)
     return c;
 }
 
+// The closure coefficient A of eq. (pg-eos): A = 0 selects the default
+// A = Cv / (3 kB), the paper's ideal-gas entropy with kB restored in its
+// density term (a parameter so that the textbook value 2 Cv / 3 can be used)
+static double resolved_A(const sdpd_params *P)
+{
+    return P->A == 0.0 ? P->Cv / (3.0 * P->kB) : P->A;
+}
+
 static int check_params(const sdpd_params *P, int nc[3])
 {
     if (!P) return SDPD_EINVAL;
     if (P->n < 0 || P->n > 0x7fffffffLL) return SDPD_EINVAL;
     if (!valid_positive(P->m) || !valid_positive(P->h) || !valid_positive(P->kB) ||
-        !valid_positive(P->Cv) || !valid_positive(P->A) || !valid_positive(P->rho0) ||
+        !valid_positive(P->Cv) || !valid_positive(P->rho0) ||
         !valid_positive(P->dt) || !valid_positive(P->eta))
         return SDPD_EINVAL;
+    if (!valid_positive(resolved_A(P))) return SDPD_EINVAL;
     if (!(P->Cv > 0.5 * P->kB)) return SDPD_EINVAL;           // d_ij < 1
     if (!(isfinite(P->zeta) && P->zeta >= 0.0 && P->zeta < 5.0 * P->eta / 3.0))
         return SDPD_EINVAL;                                   // kappa_perp > 0
@@ -206,14 +215,14 @@ static void record_to_stats(const double *rec, sdpd_stats *st)
     st->negeps = cnt[CNT_NEGEPS];
 }
 
-static int ensure_records(sdpd_ctx *c, int64_t count)
+// per-step observable records kept on the device by sdpd_step (allocated
+// once, at context creation)
+static const int64_t STEP_RECORDS = 64;
+
+static int alloc_records(sdpd_ctx *c)
 {
-    if (count <= c->obs_cap) return SDPD_OK;
-    if (c->obs_out) (void)hipFree(c->obs_out);
-    c->obs_out = nullptr;
-    c->obs_cap = 0;
-    int rc = dalloc(&c->obs_out, (size_t)(count * REC));
-    if (!rc) c->obs_cap = count;
+    int rc = dalloc(&c->obs_out, (size_t)(STEP_RECORDS * REC));
+    if (!rc) c->obs_cap = STEP_RECORDS;
     return rc;
 }
 
@@ -250,7 +259,8 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     sdpd_ctx *c = new (std::nothrow) sdpd_ctx();
     if (!c) return SDPD_ENOMEM;
     c->prm = *params;
-    derive(params, nc, c->dp);
+    c->prm.A = resolved_A(params);
+    derive(&c->prm, nc, c->dp);
     c->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -297,7 +307,7 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     rc = rc ? rc : dalloc(&c->counters, (size_t)CNT_N);
     rc = rc ? rc : dalloc(&c->err, 1);
     rc = rc ? rc : dalloc(&c->obs_partial, (size_t)c->obs_blocks * 6);
-    rc = rc ? rc : ensure_records(c, 64);
+    rc = rc ? rc : alloc_records(c);
     rc = rc ? rc : dalloc(&c->dparams, 1);
     rc = rc ? rc : dalloc(&c->task_count, (size_t)NMASK * nce);
     rc = rc ? rc : dalloc(&c->task_np, (size_t)NMASK * nce);
@@ -421,28 +431,37 @@ int sdpd_step(sdpd_ctx *c, const sdpd_state *s, uint64_t step0, int nsteps, sdpd
 {
     if (!c || !state_ok(c, s) || nsteps < 0 || !c->cells_valid) return SDPD_EINVAL;
     int rc;
-    if (per_step && (rc = ensure_records(c, nsteps))) return rc;
-    for (int k = 0; k < nsteps; ++k) {
-        if ((rc = enqueue_step(c, s, step0 + (uint64_t)k, true))) return rc;
-        if (per_step) {
+    if (!per_step) {
+        for (int k = 0; k < nsteps; ++k)
+            if ((rc = enqueue_step(c, s, step0 + (uint64_t)k, true))) return rc;
+        return SDPD_OK;
+    }
+    if (nsteps == 0) return SDPD_OK;
+    double *host = new (std::nothrow) double[(size_t)nsteps * REC];
+    if (!host) return SDPD_ENOMEM;
+    // the context's record buffer holds obs_cap steps: records go to the
+    // host in chunks of that many steps (the copy of a chunk is ordered on
+    // the stream before the next chunk overwrites the buffer)
+    rc = SDPD_OK;
+    for (int k0 = 0; k0 < nsteps && !rc; k0 += (int)c->obs_cap) {
+        const int kn = std::min((int)c->obs_cap, nsteps - k0);
+        for (int k = 0; k < kn && !rc; ++k) {
+            rc = enqueue_step(c, s, step0 + (uint64_t)(k0 + k), true);
+            if (rc) break;
             timer_begin(c, TK_OBSERVE);
             rc = run_observe(c, s, c->obs_out + (size_t)k * REC);
             timer_end(c, TK_OBSERVE);
-            if (rc) return rc;
         }
-    }
-    if (per_step && nsteps > 0) {
-        double *host = new (std::nothrow) double[(size_t)nsteps * REC];
-        if (!host) return SDPD_ENOMEM;
-        rc = check_hip(hipMemcpyAsync(host, c->obs_out, sizeof(double) * REC * (size_t)nsteps,
-                                      hipMemcpyDeviceToHost, c->stream));
-        int rc2 = take_error(c);
         if (!rc)
-            for (int k = 0; k < nsteps; ++k) record_to_stats(host + (size_t)k * REC, &per_step[k]);
-        delete[] host;
-        return rc ? rc : rc2;
+            rc = check_hip(hipMemcpyAsync(host + (size_t)k0 * REC, c->obs_out,
+                                          sizeof(double) * REC * (size_t)kn,
+                                          hipMemcpyDeviceToHost, c->stream));
     }
-    return SDPD_OK;
+    const int rc2 = take_error(c);
+    if (!rc)
+        for (int k = 0; k < nsteps; ++k) record_to_stats(host + (size_t)k * REC, &per_step[k]);
+    delete[] host;
+    return rc ? rc : rc2;
 }
 
 int sdpd_observe(sdpd_ctx *c, const sdpd_state *s, sdpd_stats *out)

@@ -138,7 +138,7 @@ class SdpdParams:
     h: float = 2.5
     kB: float = 1.0
     Cv: float = 10.0
-    A: float = None          # default Cv / (3 kB)
+    A: float = 0.0           # 0: the library's default Cv / (3 kB)
     rho0: float = 1.0
     eta: float = 1.0
     zeta: float = 0.0
@@ -153,9 +153,9 @@ class SdpdParams:
     ncell: tuple = (0, 0, 0)
 
     def c(self) -> _Params:
-        A = self.A if self.A is not None else self.Cv / (3.0 * self.kB)
         box = tuple(self.box) if np.ndim(self.box) else (float(self.box),) * 3
-        return _Params(int(self.n), (C.c_double * 3)(*box), self.m, self.h, self.kB, self.Cv, A,
+        return _Params(int(self.n), (C.c_double * 3)(*box), self.m, self.h, self.kB, self.Cv,
+                       0.0 if self.A is None else float(self.A),
                        self.rho0, self.eta, self.zeta, self.dt, int(self.fd_every),
                        int(self.kernel), int(self.fd), int(self.prec), int(self.seed),
                        int(self.replica), int(self.cell_cap), (C.c_int32 * 3)(*self.ncell))

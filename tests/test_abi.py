@@ -77,6 +77,7 @@ BAD = [
     dict(kernel=3),
     dict(fd_every=0),
     dict(dt=-1.0),
+    dict(A=-1.0),                      # A = 0 is the default, A < 0 is refused
     dict(n=-1),
     dict(prec=2),
 ]
