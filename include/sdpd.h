@@ -180,6 +180,27 @@ int sdpd_step(sdpd_ctx *ctx, const sdpd_state *state, uint64_t step0, int nsteps
 /* Observables of the current state (sync): E, Eint, KE, P, min_eps.       */
 int sdpd_observe(sdpd_ctx *ctx, const sdpd_state *state, sdpd_stats *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * observables of sdpd_observe (the total energy E = sum eps + |p|^2/2m and
+ * the total momentum of Sec. 2.2.1) for any state, without a context and
+ * without allocating anything.  params must pass the checks of sdpd_create
+ * (only n and m are used); state->p (3 x n) and state->eps (n) are read, the
+ * other state pointers are not used.  out: DEVICE array of 7 doubles that
+ * receives E, Eint, KE, P[0], P[1], P[2], min_eps (min_eps = +inf for n = 0).
+ * Asynchronous on hip_stream (NULL = the default stream): no synchronisation,
+ * capturable in a HIP graph; errors of the launch are returned, nothing is
+ * sticky.  Limits: n <= SDPD_OBSERVE_NOALLOC_MAX_N (SDPD_EINVAL beyond);
+ * the partial sums (at most 1024 blocks x 6 doubles, 48 KiB) live in a fixed
+ * device array of the library, one per device, kept until the process ends:
+ * calls that overlap on one device (two streams, two threads) race on it and
+ * must be ordered by the caller.  The sums are those of sdpd_observe, in the
+ * same order, so the values are bit for bit identical.  SDPD_EINVAL for bad
+ * parameters or NULL pointers, SDPD_EHIP for a failed launch.               */
+#define SDPD_OBSERVE_NOALLOC_MAX_N 0x7fffffffLL
+int sdpd_observe_noalloc(const sdpd_params *params, const sdpd_state *state, void *hip_stream,
+                         double *out);
+
 /* Wait for the context's stream and return (then clear) the first sticky
  * device error, or SDPD_OK.                                               */
 int sdpd_sync(sdpd_ctx *ctx);

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "sdpd_internal.hpp"
@@ -270,7 +271,7 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     c->ncell = c->dp.ncell;
     const size_t n = (size_t)c->n, nce = (size_t)c->ncell;
     c->nscan_blocks = (int64_t)(((size_t)NMASK * nce + 1023) / 1024) + 1;
-    c->obs_blocks = c->n > 0 ? std::min<int64_t>(1024, (c->n + 255) / 256) : 1;
+    c->obs_blocks = std::max(observe_blocks(c->n), 1);
     {
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) !=
@@ -476,6 +477,61 @@ int sdpd_observe(sdpd_ctx *c, const sdpd_state *s, sdpd_stats *out)
     rc = take_error(c);
     record_to_stats(rec, out);
     return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of sdpd_observe_noalloc: the per-block partial sums (6 doubles per
+// block, at most OBS_MAX_BLOCKS blocks: 48 KiB).  Each device holds its own
+// copy until the process ends.  In host code `scratch` only names the
+// symbol: kernels and copies use the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+static __device__ __align__(256) double scratch[(size_t)sdpd::OBS_MAX_BLOCKS * 6];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices];
+
+// the current device's address of `scratch` (looked up on the first call on
+// that device)
+int scratch_address(double **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return SDPD_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return SDPD_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SDPD_EHIP;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SDPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdpd_observe_noalloc(const sdpd_params *params, const sdpd_state *s, void *hip_stream,
+                         double *out)
+{
+    int nc[3];
+    int rc = check_params(params, nc);
+    if (rc) return rc;
+    if (!s || !out || (params->n > 0 && (!s->p || !s->eps))) return SDPD_EINVAL;
+    if (params->n > SDPD_OBSERVE_NOALLOC_MAX_N) return SDPD_EINVAL;
+    if ((int64_t)observe_blocks(params->n) * 6 > (int64_t)(sizeof(scratch) / sizeof(double)))
+        return SDPD_EINVAL;
+    double *partial = nullptr;
+    if ((rc = scratch_address(&partial))) return rc;
+    sdpd_params prm = *params;
+    prm.A = resolved_A(params);
+    DevParams dp;
+    derive(&prm, nc, dp);
+    return launch_observe(dp, s->p, s->eps, partial, nullptr, out, (hipStream_t)hip_stream);
 }
 
 int sdpd_sync(sdpd_ctx *c)

@@ -5,6 +5,8 @@
 
 #include <float.h>
 
+#include <algorithm>
+
 namespace sdpd {
 
 // F(r) with grad W(r) = -F(|r|) r, for 0 < r < h (Sec. 2.1.1; the cubic
@@ -169,18 +171,29 @@ __global__ __launch_bounds__(OBS_THREADS) void k_observe_final(const double *par
     rec[4] = s[3][0];
     rec[5] = s[4][0];
     rec[6] = s[5][0];
+    if (!counters) return;   // a record without the F/D counters (7 doubles)
     unsigned long long *ci = reinterpret_cast<unsigned long long *>(rec + 7);
     for (int k = 0; k < CNT_N; ++k) ci[k] = counters[k];
 }
 
+int observe_blocks(int64_t n) { return n > 0 ? (int)std::min<int64_t>(OBS_MAX_BLOCKS, (n + 255) / 256) : 0; }
+
+int launch_observe(const DevParams &dp, const double *p, const double *eps, double *partial,
+                   const unsigned long long *counters, double *dst_record, hipStream_t stream)
+{
+    const int nb = observe_blocks(dp.n);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_observe_partial, dim3((unsigned)nb), dim3(OBS_THREADS), 0, stream,
+                           dp, p, eps, partial);
+    hipLaunchKernelGGL(k_observe_final, dim3(1), dim3(OBS_THREADS), 0, stream, partial,
+                       (int64_t)nb, counters, dst_record);
+    return check_hip(hipGetLastError());
+}
+
 int run_observe(sdpd_ctx *c, const sdpd_state *s, double *dst_record)
 {
-    if (c->n > 0)
-        hipLaunchKernelGGL(k_observe_partial, dim3((unsigned)c->obs_blocks), dim3(OBS_THREADS), 0,
-                           c->stream, c->dp, s->p, s->eps, c->obs_partial);
-    hipLaunchKernelGGL(k_observe_final, dim3(1), dim3(OBS_THREADS), 0, c->stream, c->obs_partial,
-                       c->n > 0 ? c->obs_blocks : 0, c->counters, dst_record);
-    return check_hip(hipGetLastError());
+    return launch_observe(c->dp, s->p, s->eps, c->obs_partial, c->counters, dst_record,
+                          c->stream);
 }
 
 }  // namespace sdpd

@@ -158,6 +158,13 @@ int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t);
 int fd_prepare_sweep(sdpd_ctx *c);   // after any change of the tuning
 bool fd_one_launch(const sdpd_ctx *c);   // the sweep runs as one launch
 int run_observe(sdpd_ctx *c, const sdpd_state *s, double *dst_record);
+// observables of n = dp.n particles into dst_record (REC doubles, or the
+// first 7 when counters is NULL); partial holds 6 doubles per block of
+// observe_blocks(n) <= OBS_MAX_BLOCKS blocks
+constexpr int OBS_MAX_BLOCKS = 1024;
+int observe_blocks(int64_t n);
+int launch_observe(const DevParams &dp, const double *p, const double *eps, double *partial,
+                   const unsigned long long *counters, double *dst_record, hipStream_t stream);
 void adjoint_free(AdjointWork *a);
 
 // event timing around one launch of class k (no-op unless c->timing)

@@ -28,7 +28,7 @@ EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
            "sdpd_set_timing_mask",
            "sdpd_batch_create", "sdpd_batch_run",
            "sdpd_batch_destroy", "sdpd_adjoint_forward", "sdpd_adjoint_backward",
-           "sdpd_strerror",
+           "sdpd_observe_noalloc", "sdpd_strerror",
            "sdpd_abi_version")
 
 
@@ -106,6 +106,7 @@ def lib():
             "sdpd_batch_destroy": [vp],
             "sdpd_adjoint_forward": [vp, SP, i32, i32],
             "sdpd_adjoint_backward": [vp, vp, vp, vp, vp, vp, C.POINTER(C.c_double)],
+            "sdpd_observe_noalloc": [C.POINTER(_Params), SP, vp, vp],
             "sdpd_abi_version": [],
         }
         for name, args in sig.items():
@@ -190,6 +191,20 @@ class DeviceState:
                 raise ValueError("state tensors must be contiguous device tensors")
         return _State(self.q.data_ptr(), self.p.data_ptr(), self.eps.data_ptr(),
                       self.rho.data_ptr(), self.f.data_ptr(), self.id.data_ptr())
+
+
+def observe_noalloc(params: SdpdParams, s: DeviceState, out, stream=None):
+    """sdpd_observe_noalloc: E, Eint, KE, P (3), min eps of s into the float64
+    device tensor out (7 elements), on stream (default: torch's current)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+            and out.numel() >= 7):
+        raise ValueError("out must be a contiguous float64 device tensor of 7 elements")
+    _check(lib().sdpd_observe_noalloc(C.byref(params.c()), C.byref(s.c()),
+                                      C.c_void_p(stream.cuda_stream), C.c_void_p(out.data_ptr())),
+           "sdpd_observe_noalloc")
 
 
 class Context:
