@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SDPD_ABI_VERSION 5
+#define SDPD_ABI_VERSION 6
 
 typedef enum {
     SDPD_OK = 0,
@@ -317,6 +317,36 @@ int sdpd_batch_destroy(sdpd_batch *batch);
 int sdpd_adjoint_forward(sdpd_ctx *ctx, sdpd_state *state, int nsteps, int checkpoint_every);
 int sdpd_adjoint_backward(sdpd_ctx *ctx, const double *dJ_dq, const double *dJ_dp,
                           double *dJ_dq0, double *dJ_dp0, double *dJ_deps0, double *dJ_dA);
+
+/* The reverse pass of sdpd_adjoint_backward for a J that may also read the
+ * final internal energies and densities, e.g. the mean pressure
+ * P = A kB rho eps / (m Cv) of the closure of Sec. 2.1.2 with eq. (pg-eos).
+ * ct: cotangents dJ/dq_K, dJ/dp_K (DEVICE, 3 x n, by id; required) and
+ * dJ/deps_K, dJ/drho_K (DEVICE, n, by id; NULL = zero).  The final energies
+ * follow the final densities at the entropies fixed by the initial state
+ * (eps_K = eps0 (rho_K / rho(q0))^(A kB/Cv), Sec. 3.1), so dJ/deps_K reaches
+ * q0 through both densities and eps0 through the entropies.
+ * gr: dq0, dp0 (DEVICE, 3 x n, by id; required), deps0 (DEVICE, n, by id;
+ * may be NULL) receive the gradients; the host scalars dA, dCv and drho0
+ * receive the gradients with respect to the closure coefficient A, the heat
+ * capacity Cv at fixed A (the conservative dynamics depends on them only
+ * through A/Cv, so dCv = -(A/Cv) dA; with the default A = Cv/(3 kB) tied to
+ * Cv the total derivative along the tie, dCv + dA/(3 kB), is zero) and the
+ * reference density rho0 of eq. (pg-eos) (zero: rho0 cancels from the
+ * dynamics).  These are the derivatives through the dynamics; terms of J's
+ * own explicit dependence on A or Cv are the caller's.  Synchronises.
+ * SDPD_EINVAL without a preceding sdpd_adjoint_forward or for NULL required
+ * pointers.                                                                */
+typedef struct {
+    const double *dq, *dp;     /* 3 x n, required                          */
+    const double *deps, *drho; /* n, NULL = zero                           */
+} sdpd_cotangent;
+typedef struct {
+    double *dq0, *dp0;         /* 3 x n, required                          */
+    double *deps0;             /* n, may be NULL                           */
+    double dA, dCv, drho0;     /* host outputs                             */
+} sdpd_gradient;
+int sdpd_adjoint_vjp(sdpd_ctx *ctx, const sdpd_cotangent *ct, sdpd_gradient *gr);
 
 /* Size of the pair schedule of the last F/D sweep (sync): the number of
  * active pairs and the number of particle entries the phase workgroups

@@ -22,6 +22,17 @@
 // and dJ/dA = sum_k G_k / A + (kB/Cv)(H_k - G_k ln rho0_k).  The reference
 // density rho0 cancels (eps depends on eps0 and rho / rho0_k only).
 //
+// Cotangents of the final energies and densities (J may read eps_K, rho_K,
+// e.g. the mean pressure of the closure of Sec. 2.1.2): since
+// eps_K = c rho_K^g, epsbar_K adds g epsbar eps_K / rho_K to rhobar_K, which
+// together with the caller's rhobar_K enters the density term of the final
+// configuration's q product, and epsbar eps_K to the cotangent of ln c
+// (Ge), which joins G on the initial-state path; its A part is
+// (kB/Cv)(He - Ge ln rho0) with He = Ge ln rho_K (no 1/A term: eps has no
+// A prefactor).  The conservative dynamics depends on A and Cv only through
+// A/Cv (g = A kB/Cv, kap = A kB/(m Cv)), so at fixed A
+// dJ/dCv = -(A/Cv) dJ/dA for a J without an explicit Cv dependence.
+//
 // Forward: checkpoints of the full state every `every` steps; backward:
 // each segment is recomputed from its checkpoint (bit-identical: the same
 // kernels on the same data), its configurations kept, and processed in
@@ -31,6 +42,7 @@
 #include <algorithm>
 
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "sdpd_internal.hpp"
@@ -48,6 +60,7 @@ struct AdjointWork {
     std::vector<StateBuf> ckpt, seg;
     StateBuf w;
     double *lq = nullptr, *lp = nullptr, *G = nullptr, *H = nullptr;   // id order
+    double *Ge = nullptr, *He = nullptr;   // final-energy path (id order)
     double *eps0 = nullptr, *rho0 = nullptr;                             // id order
     double *vc = nullptr, *wc = nullptr, *pibar = nullptr, *rhobar = nullptr;   // cell order
     uint32_t *idcount = nullptr;
@@ -269,22 +282,45 @@ __global__ __launch_bounds__(256) void k_vjp_q(DevParams P, const double *__rest
     w[2 * n + i] = wz;
 }
 
-// G -> eps0bar = G / eps0 and rho0bar = -g G / rho0 (id order, in place into
-// the given outputs)
-__global__ void k_initial_path(int64_t n, double g, const double *G, const double *eps0,
-                               const double *rho0, double *eps0bar, double *rho0bar)
+// cotangents of the final energies and densities (id order, either may be
+// NULL) at the final configuration (cell order): rhobar += drho + g deps
+// eps / rho, Ge = deps eps, He = Ge ln rho
+__global__ void k_final_cotangent(int64_t n, double g, const uint32_t *id, const double *deps,
+                                  const double *drho, const double *eps, const double *rho,
+                                  double *rhobar, double *Ge, double *He)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    if (eps0bar) eps0bar[k] = G[k] / eps0[k];
-    rho0bar[k] = -g * G[k] / rho0[k];
+    const int64_t i = id[k];
+    const double de = deps ? deps[i] : 0.0;
+    const double dr = drho ? drho[i] : 0.0;
+    rhobar[k] += dr + g * de * eps[k] / rho[k];
+    const double ge = de * eps[k];
+    Ge[i] = ge;
+    He[i] = ge * log(rho[k]);
+}
+
+// (G + Ge) -> eps0bar = (G + Ge) / eps0 and rho0bar = -g (G + Ge) / rho0
+// (id order, into the given outputs)
+__global__ void k_initial_path(int64_t n, double g, const double *G, const double *Ge,
+                               const double *eps0, const double *rho0, double *eps0bar,
+                               double *rho0bar)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double gt = G[k] + Ge[k];
+    if (eps0bar) eps0bar[k] = gt / eps0[k];
+    rho0bar[k] = -g * gt / rho0[k];
 }
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // one vector-Jacobian product of the force at configuration X (already in
-// W): lq += weight * Jf(q)^T (h lp), G and H accumulate
-static int vjp_config(sdpd_ctx *c, AdjointWork *a, const sdpd_state &Ws, double weight)
+// W): lq += weight * Jf(q)^T (h lp), G and H accumulate.  At the final
+// configuration (weight 1) the cotangents of the final energies and
+// densities (deps, drho: id order, may be NULL) join the density term.
+static int vjp_config(sdpd_ctx *c, AdjointWork *a, const sdpd_state &Ws, double weight,
+                      const double *deps = nullptr, const double *drho = nullptr)
 {
     const int64_t n = c->n;
     int rc;
@@ -296,6 +332,10 @@ static int vjp_config(sdpd_ctx *c, AdjointWork *a, const sdpd_state &Ws, double 
     hipLaunchKernelGGL(k_vjp_pi, dim3(nblk(n)), dim3(256), 0, c->stream, c->dp, Ws.q, a->vc,
                        Ws.eps, Ws.rho, Ws.id, c->cell_sorted, c->cell_start, c->masks, weight,
                        a->pibar, a->rhobar, a->G, a->H);
+    if (deps || drho)
+        hipLaunchKernelGGL(k_final_cotangent, dim3(nblk(n)), dim3(256), 0, c->stream, n,
+                           c->dp.eps_exp, Ws.id, deps, drho, Ws.eps, Ws.rho, a->rhobar, a->Ge,
+                           a->He);
     hipLaunchKernelGGL(k_vjp_q, dim3(nblk(n)), dim3(256), 0, c->stream, c->dp, Ws.q, a->vc,
                        Ws.eps, Ws.rho, a->rhobar, c->cell_sorted, c->cell_start, c->masks, 1,
                        a->wc);
@@ -333,7 +373,8 @@ int sdpd_adjoint_forward(sdpd_ctx *c, sdpd_state *s, int nsteps, int every)
     if (!rc) rc = state_alloc(a, a->w, n);
     for (double **p : {&a->lq, &a->lp, &a->vc, &a->wc})
         if (!rc) rc = walloc(a, (void **)p, sizeof(double) * 3 * n);
-    for (double **p : {&a->G, &a->H, &a->eps0, &a->rho0, &a->pibar, &a->rhobar})
+    for (double **p : {&a->G, &a->H, &a->Ge, &a->He, &a->eps0, &a->rho0, &a->pibar,
+                       &a->rhobar})
         if (!rc) rc = walloc(a, (void **)p, sizeof(double) * n);
     if (!rc) rc = walloc(a, (void **)&a->idcount, sizeof(uint32_t) * n);
     if (rc) {
@@ -357,10 +398,17 @@ int sdpd_adjoint_forward(sdpd_ctx *c, sdpd_state *s, int nsteps, int every)
     return SDPD_OK;
 }
 
-int sdpd_adjoint_backward(sdpd_ctx *c, const double *dJ_dq, const double *dJ_dp, double *dJ_dq0,
-                          double *dJ_dp0, double *dJ_deps0, double *dJ_dA)
+}  // extern "C"
+
+namespace sdpd {
+
+// reverse pass from the cotangents of the final state (q, p: 3 x n; eps,
+// rho: n; id order; q, p required, eps, rho may be NULL); dA and dCv (host,
+// may be NULL) synchronise
+static int adjoint_backward(sdpd_ctx *c, const double *dJ_dq, const double *dJ_dp,
+                            const double *dJ_deps, const double *dJ_drho, double *dJ_dq0,
+                            double *dJ_dp0, double *dJ_deps0, double *dJ_dA, double *dJ_dCv)
 {
-    if (!c || !c->adj || !dJ_dq || !dJ_dp || !dJ_dq0 || !dJ_dp0) return SDPD_EINVAL;
     AdjointWork *a = c->adj;
     const int64_t n = c->n;
     const size_t d3 = sizeof(double) * 3 * (size_t)n;
@@ -369,8 +417,8 @@ int sdpd_adjoint_backward(sdpd_ctx *c, const double *dJ_dq, const double *dJ_dp,
         return rc;
     if ((rc = check_hip(hipMemcpyAsync(a->lp, dJ_dp, d3, hipMemcpyDeviceToDevice, c->stream))))
         return rc;
-    if ((rc = launch_fill_u64(c, (unsigned long long *)a->G, 0ull, n))) return rc;
-    if ((rc = launch_fill_u64(c, (unsigned long long *)a->H, 0ull, n))) return rc;
+    for (double *z : {a->G, a->H, a->Ge, a->He})
+        if ((rc = launch_fill_u64(c, (unsigned long long *)z, 0ull, n))) return rc;
     const sdpd_state Ws = a->w.view();
     const double dt_m = c->prm.dt / c->prm.m;
     for (int sg = a->nck - 1; sg >= 0; --sg) {
@@ -385,7 +433,7 @@ int sdpd_adjoint_backward(sdpd_ctx *c, const double *dJ_dq, const double *dJ_dp,
         }
         if (sg == a->nck - 1) {   // the final configuration: second half kick of step K-1
             if ((rc = copy_state(c, a->w, a->seg[end - start].view()))) return rc;
-            if ((rc = vjp_config(c, a, Ws, 1.0))) return rc;
+            if ((rc = vjp_config(c, a, Ws, 1.0, dJ_deps, dJ_drho))) return rc;
         }
         for (int N = end - 1; N >= start; --N) {
             hipLaunchKernelGGL(k_axpy, dim3(nblk(3 * n)), dim3(256), 0, c->stream, 3 * n, dt_m,
@@ -397,7 +445,7 @@ int sdpd_adjoint_backward(sdpd_ctx *c, const double *dJ_dq, const double *dJ_dp,
     // initial-state path: the entropies come from eps0 and rho(q0)
     const double g = c->dp.eps_exp;
     double *eps0bar = dJ_deps0;
-    hipLaunchKernelGGL(k_initial_path, dim3(nblk(n)), dim3(256), 0, c->stream, n, g, a->G,
+    hipLaunchKernelGGL(k_initial_path, dim3(nblk(n)), dim3(256), 0, c->stream, n, g, a->G, a->Ge,
                        a->eps0, a->rho0, eps0bar, a->rhobar);   // rhobar: id order here
     // W holds configuration 0 with its cells and masks (last vjp_config)
     hipLaunchKernelGGL(k_gather_id, dim3(nblk(n)), dim3(256), 0, c->stream, n, 1, Ws.id, 1.0,
@@ -412,24 +460,51 @@ int sdpd_adjoint_backward(sdpd_ctx *c, const double *dJ_dq, const double *dJ_dp,
         return rc;
     if ((rc = check_hip(hipMemcpyAsync(dJ_dp0, a->lp, d3, hipMemcpyDeviceToDevice, c->stream))))
         return rc;
-    if (dJ_dA) {
-        std::vector<double> G(n), H(n), r0(n);
-        rc = check_hip(hipMemcpyAsync(G.data(), a->G, sizeof(double) * n, hipMemcpyDeviceToHost,
-                                      c->stream));
-        if (!rc)
-            rc = check_hip(hipMemcpyAsync(H.data(), a->H, sizeof(double) * n,
-                                          hipMemcpyDeviceToHost, c->stream));
-        if (!rc)
-            rc = check_hip(hipMemcpyAsync(r0.data(), a->rho0, sizeof(double) * n,
-                                          hipMemcpyDeviceToHost, c->stream));
+    if (dJ_dA || dJ_dCv) {
+        std::vector<double> G(n), H(n), Ge(n), He(n), r0(n);
+        const std::pair<double *, const double *> cp[] = {
+            {G.data(), a->G}, {H.data(), a->H}, {Ge.data(), a->Ge}, {He.data(), a->He},
+            {r0.data(), a->rho0}};
+        for (const auto &x : cp)
+            if (!rc)
+                rc = check_hip(hipMemcpyAsync(x.first, x.second, sizeof(double) * n,
+                                              hipMemcpyDeviceToHost, c->stream));
         if (!rc) rc = check_hip(hipStreamSynchronize(c->stream));
         if (rc) return rc;
         const double kc = c->prm.kB / c->prm.Cv;
         double acc = 0.0;
-        for (int64_t k = 0; k < n; ++k) acc += G[k] / c->dp.A + kc * (H[k] - G[k] * log(r0[k]));
-        *dJ_dA = acc;
+        for (int64_t k = 0; k < n; ++k) {
+            const double lr0 = log(r0[k]);
+            acc += G[k] / c->dp.A + kc * (H[k] - G[k] * lr0) + kc * (He[k] - Ge[k] * lr0);
+        }
+        if (dJ_dA) *dJ_dA = acc;
+        if (dJ_dCv) *dJ_dCv = -(c->dp.A / c->prm.Cv) * acc;
     }
     return SDPD_OK;
+}
+
+}  // namespace sdpd
+
+extern "C" {
+
+int sdpd_adjoint_backward(sdpd_ctx *c, const double *dJ_dq, const double *dJ_dp, double *dJ_dq0,
+                          double *dJ_dp0, double *dJ_deps0, double *dJ_dA)
+{
+    if (!c || !c->adj || !dJ_dq || !dJ_dp || !dJ_dq0 || !dJ_dp0) return SDPD_EINVAL;
+    return adjoint_backward(c, dJ_dq, dJ_dp, nullptr, nullptr, dJ_dq0, dJ_dp0, dJ_deps0, dJ_dA,
+                            nullptr);
+}
+
+int sdpd_adjoint_vjp(sdpd_ctx *c, const sdpd_cotangent *ct, sdpd_gradient *gr)
+{
+    if (!c || !c->adj || !ct || !gr || !ct->dq || !ct->dp || !gr->dq0 || !gr->dp0)
+        return SDPD_EINVAL;
+    gr->dA = gr->dCv = gr->drho0 = 0.0;
+    int rc = adjoint_backward(c, ct->dq, ct->dp, ct->deps, ct->drho, gr->dq0, gr->dp0, gr->deps0,
+                              &gr->dA, &gr->dCv);
+    if (!rc) rc = check_hip(hipStreamSynchronize(c->stream));
+    gr->drho0 = 0.0;   // rho0 cancels from the dynamics (eps depends on rho/rho0_k only)
+    return rc;
 }
 
 }  // extern "C"

@@ -28,7 +28,7 @@ EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
            "sdpd_set_timing_mask",
            "sdpd_batch_create", "sdpd_batch_run",
            "sdpd_batch_destroy", "sdpd_adjoint_forward", "sdpd_adjoint_backward",
-           "sdpd_observe_noalloc", "sdpd_strerror",
+           "sdpd_adjoint_vjp", "sdpd_observe_noalloc", "sdpd_strerror",
            "sdpd_abi_version")
 
 
@@ -57,6 +57,16 @@ class _Stats(C.Structure):
                 ("rej_ratio", C.c_uint64), ("marginal", C.c_uint64), ("negeps", C.c_uint64),
                 ("E", C.c_double), ("Eint", C.c_double), ("KE", C.c_double),
                 ("P", C.c_double * 3), ("min_eps", C.c_double)]
+
+
+class _Cotangent(C.Structure):
+    _fields_ = [("dq", C.c_void_p), ("dp", C.c_void_p), ("deps", C.c_void_p),
+                ("drho", C.c_void_p)]
+
+
+class _Gradient(C.Structure):
+    _fields_ = [("dq0", C.c_void_p), ("dp0", C.c_void_p), ("deps0", C.c_void_p),
+                ("dA", C.c_double), ("dCv", C.c_double), ("drho0", C.c_double)]
 
 
 def _stats(s: _Stats) -> dict:
@@ -106,6 +116,7 @@ def lib():
             "sdpd_batch_destroy": [vp],
             "sdpd_adjoint_forward": [vp, SP, i32, i32],
             "sdpd_adjoint_backward": [vp, vp, vp, vp, vp, vp, C.POINTER(C.c_double)],
+            "sdpd_adjoint_vjp": [vp, C.POINTER(_Cotangent), C.POINTER(_Gradient)],
             "sdpd_observe_noalloc": [C.POINTER(_Params), SP, vp, vp],
             "sdpd_abi_version": [],
         }
@@ -338,6 +349,25 @@ class Context:
                                            dp0.data_ptr(), de0.data_ptr(), C.byref(dA)),
                "sdpd_adjoint_backward")
         return dq0, dp0, de0, dA.value
+
+    def adjoint_vjp(self, dq, dp, deps=None, drho=None):
+        """Reverse pass from the cotangents of the final state, all float64
+        device tensors indexed by particle id: dq, dp (3, n) and optionally
+        deps, drho (n,).  Returns a dict with dq0, dp0 (3, n), deps0 (n,)
+        tensors and the scalars dA, dCv (at fixed A) and drho0."""
+        import torch
+        n = dq.shape[1]
+        out = {"dq0": torch.empty((3, n), dtype=torch.float64, device=dq.device),
+               "dp0": torch.empty((3, n), dtype=torch.float64, device=dq.device),
+               "deps0": torch.empty((n,), dtype=torch.float64, device=dq.device)}
+        keep = [t.contiguous() if t is not None else None for t in (dq, dp, deps, drho)]
+        ptr = lambda t: None if t is None else t.data_ptr()
+        ct = _Cotangent(*[ptr(t) for t in keep])
+        gr = _Gradient(out["dq0"].data_ptr(), out["dp0"].data_ptr(), out["deps0"].data_ptr(),
+                       0.0, 0.0, 0.0)
+        _check(lib().sdpd_adjoint_vjp(self._h, C.byref(ct), C.byref(gr)), "sdpd_adjoint_vjp")
+        out.update(dA=gr.dA, dCv=gr.dCv, drho0=gr.drho0)
+        return out
 
     def fd_schedule_size(self):
         """(active pairs, staged particle entries) of the last F/D sweep."""

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_messages():
     L = sdpd.lib()
-    assert L.sdpd_abi_version() == 5
+    assert L.sdpd_abi_version() == 6
     for rc in (0, -1, -2, -3, -4, -5, -6):
         assert L.sdpd_strerror(rc)
     assert L.sdpd_strerror(-99) == b"unknown status"
@@ -45,11 +45,14 @@ def test_struct_layout_matches_header(tmp_path):
     fields = [("sdpd_params", f) for f, _ in sdpd._Params._fields_] + \
              [("sdpd_state", f) for f, _ in sdpd._State._fields_] + \
              [("sdpd_stats", f) for f, _ in sdpd._Stats._fields_] + \
-             [("sdpd_tuning", f) for f, _ in sdpd._Tuning._fields_]
+             [("sdpd_tuning", f) for f, _ in sdpd._Tuning._fields_] + \
+             [("sdpd_cotangent", f) for f, _ in sdpd._Cotangent._fields_] + \
+             [("sdpd_gradient", f) for f, _ in sdpd._Gradient._fields_]
     body = "\n".join(f'printf("%zu\\n", offsetof({t}, {f}));' for t, f in fields)
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"sdpd.h\"\nint main(void){\n"
-                   + body + '\nprintf("%zu %zu %zu %zu\\n", sizeof(sdpd_params), sizeof(sdpd_state),'
-                   ' sizeof(sdpd_stats), sizeof(sdpd_tuning));\nreturn 0;}\n')
+                   + body + '\nprintf("%zu %zu %zu %zu %zu %zu\\n", sizeof(sdpd_params),'
+                   ' sizeof(sdpd_state), sizeof(sdpd_stats), sizeof(sdpd_tuning),'
+                   ' sizeof(sdpd_cotangent), sizeof(sdpd_gradient));\nreturn 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
                    check=True)
@@ -59,8 +62,10 @@ def test_struct_layout_matches_header(tmp_path):
            [getattr(sdpd._State, f).offset for f, _ in sdpd._State._fields_] + \
            [getattr(sdpd._Stats, f).offset for f, _ in sdpd._Stats._fields_] + \
            [getattr(sdpd._Tuning, f).offset for f, _ in sdpd._Tuning._fields_] + \
+           [getattr(sdpd._Cotangent, f).offset for f, _ in sdpd._Cotangent._fields_] + \
+           [getattr(sdpd._Gradient, f).offset for f, _ in sdpd._Gradient._fields_] + \
            [C.sizeof(sdpd._Params), C.sizeof(sdpd._State), C.sizeof(sdpd._Stats),
-            C.sizeof(sdpd._Tuning)]
+            C.sizeof(sdpd._Tuning), C.sizeof(sdpd._Cotangent), C.sizeof(sdpd._Gradient)]
     assert got == want
 
 

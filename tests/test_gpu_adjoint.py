@@ -144,6 +144,154 @@ def test_autograd_wrapper_matches_direct_backward():
     Jd, dq, dp, de, _ = _gpu_adjoint(q, p, eps, ids.astype(np.int64), (12.0, 12.0, 12.0), 8, 3,
                                      a, b)
     assert abs(J.item() - Jd) <= 1e-12 * abs(Jd)
-    assert np.array_equal(gq.cpu().numpy(), dq)
-    assert np.array_equal(gp.cpu().numpy(), dp)
-    assert np.array_equal(ge.cpu().numpy(), de)
+    for name, x, y in (("q", gq, dq), ("p", gp, dp), ("eps", ge, de)):
+        x = x.cpu().numpy()
+        say(f"d/d{name}0: max |autograd - direct| = {np.abs(x - y).max():.3e}")
+        assert np.array_equal(x, y), name
+
+
+# ---- the two observables of the 64^3 adjoint workload: final kinetic energy
+# and mean pressure P = A kB rho eps / (m Cv) (Sec. 2.1.2 with eq. pg-eos)
+CV, A0 = 10.0, 10.0 / 3.0
+
+
+def _observables(q, p, eps, rho, Cv=CV, A=A0):
+    n = eps.shape[0]
+    return float((p * p).sum() / 2.0), float((A * rho * eps / Cv).sum() / n)
+
+
+def _oracle_obs(q, p, eps, ids, box, K, Cv=CV, A=A0, rho0=1.0):
+    P = O.OracleParams(n=len(eps), box=box, Cv=Cv, A=A, rho0=rho0, fd_mode=O.FD_NONE)
+    S = O.State.from_arrays(q, p, eps, ids)
+    O.prepare(P, S)
+    rc, _ = O.step(P, S, 0, K)
+    assert rc == 0
+    return _observables(S.q, S.p, S.eps, S.rho, Cv, A)
+
+
+def _gpu_obs_gradients(q, p, eps, ids, box, K, every, Cv=CV, A=A0):
+    """Final observables and, for each, the adjoint gradient: dq0 (3, n) by
+    id, and dA, dCv, drho0 including the explicit terms of J_P."""
+    import torch
+    from paper_1707_04232_amd import sdpd
+    n = len(eps)
+    prm = sdpd.SdpdParams(n=n, box=box, Cv=Cv, A=A, fd=sdpd.FD_NONE)
+    S = sdpd.DeviceState.from_numpy(q, p, eps, ids)
+    out = {}
+    with sdpd.Context(prm) as ctx:
+        ctx.prepare(S)
+        ctx.adjoint_forward(S, K, every)
+        ctx.sync()
+        order = S.id.long()
+        qK = torch.empty_like(S.q)
+        pK = torch.empty_like(S.p)
+        eK = torch.empty_like(S.eps)
+        rK = torch.empty_like(S.rho)
+        qK[:, order], pK[:, order], eK[order], rK[order] = S.q, S.p, S.eps, S.rho
+        JKE, JP = _observables(qK.cpu().numpy(), pK.cpu().numpy(), eK.cpu().numpy(),
+                               rK.cpu().numpy(), Cv, A)
+        zero3 = torch.zeros_like(qK)
+        g = ctx.adjoint_vjp(zero3, pK.clone())                        # J_KE, m = 1
+        out["KE"] = (JKE, g["dq0"].cpu().numpy(), g["dA"], g["dCv"], g["drho0"])
+        c = A / (Cv * n)
+        g = ctx.adjoint_vjp(zero3, torch.zeros_like(pK), c * rK, c * eK)   # J_P
+        out["P"] = (JP, g["dq0"].cpu().numpy(), g["dA"] + JP / A, g["dCv"] - JP / Cv,
+                    g["drho0"])
+        ctx.sync()
+    return out
+
+
+def test_adjoint_c5_observables_vs_oracle_central_differences():
+    """Gradients of the final kinetic energy and of the mean pressure with
+    respect to q0, A, Cv (at fixed A) and rho0, against central differences
+    (delta = 1e-6) of the FP64 oracle's own trajectories; rho0 cancels, so
+    its gradient is zero on both sides."""
+    say("C5 observables vs oracle central differences, 10^3, K=12")
+    q, p, eps, ids = lattice_state(10, Cv=CV, T=1.0, jitter=0.2)
+    ids = ids.astype(np.int64)
+    box, K, delta = (10.0, 10.0, 10.0), 12, 1e-6
+    out = _gpu_obs_gradients(q, p, eps, ids, box, K, 5)
+    ref = _oracle_obs(q, p, eps, ids, box, K)
+    d = np.random.default_rng(3).normal(size=q.shape)
+    fq = [(x - y) / (2 * delta) for x, y in zip(_oracle_obs(q + delta * d, p, eps, ids, box, K),
+                                               _oracle_obs(q - delta * d, p, eps, ids, box, K))]
+    fA = [(x - y) / (2 * delta) for x, y in zip(_oracle_obs(q, p, eps, ids, box, K, A=A0 + delta),
+                                               _oracle_obs(q, p, eps, ids, box, K, A=A0 - delta))]
+    fC = [(x - y) / (2 * delta) for x, y in zip(_oracle_obs(q, p, eps, ids, box, K, Cv=CV + delta),
+                                               _oracle_obs(q, p, eps, ids, box, K, Cv=CV - delta))]
+    rp = _oracle_obs(q, p, eps, ids, box, K, rho0=1.0 + delta)
+    rm = _oracle_obs(q, p, eps, ids, box, K, rho0=1.0 - delta)
+    for k, name in enumerate(("KE", "P")):
+        J, dq0, dA, dCv, drho0 = out[name]
+        assert abs(J - ref[k]) <= 1e-10 * abs(ref[k])
+        ad = float((dq0[:, ids] * d).sum())
+        say(f"{name}: dq0.d adjoint {ad:.10e} oracle {fq[k]:.10e}; dA {dA:.10e} vs {fA[k]:.10e};"
+            f" dCv {dCv:.10e} vs {fC[k]:.10e}; drho0 {drho0} vs difference {rp[k] - rm[k]:.1e}")
+        assert abs(ad - fq[k]) <= 1e-6 * max(abs(fq[k]), 1e-3)
+        assert abs(dA - fA[k]) <= 1e-6 * max(abs(fA[k]), 1e-3)
+        assert abs(dCv - fC[k]) <= 1e-6 * max(abs(fC[k]), 1e-3)
+        # the reference density cancels: exactly zero from the library, and
+        # the oracle's trajectories differ only by rounding
+        assert drho0 == 0.0
+        assert abs(rp[k] - rm[k]) <= 1e-12 * abs(ref[k])
+
+
+def test_adjoint_c5_observables_gpu_central_differences_64():
+    """The 64^3, K = 50 workload: both observables' q0 gradients against
+    central differences (delta = 1e-6) of the GPU forward along a random
+    direction."""
+    from paper_1707_04232_amd import sdpd
+    say("C5 observables, 64^3, K=50, GPU central differences")
+    q, p, eps, ids = lattice_state(64, Cv=CV, T=1.0)
+    ids = ids.astype(np.int64)
+    n, box, K, delta = len(eps), (64.0, 64.0, 64.0), 50, 1e-6
+    out = _gpu_obs_gradients(q, p, eps, ids, box, K, 10)
+
+    def obs(qq):
+        prm = sdpd.SdpdParams(n=n, box=box, Cv=CV, A=A0, fd=sdpd.FD_NONE)
+        S = sdpd.DeviceState.from_numpy(qq, p, eps, ids)
+        with sdpd.Context(prm) as ctx:
+            ctx.prepare(S)
+            ctx.step(S, 0, K, stats=False)
+            ctx.sync()
+            g = S.to_numpy()
+        return _observables(g["q"], g["p"], g["eps"], g["rho"])
+
+    d = np.random.default_rng(7).normal(size=q.shape)
+    fd = [(x - y) / (2 * delta) for x, y in zip(obs(q + delta * d), obs(q - delta * d))]
+    for k, name in enumerate(("KE", "P")):
+        ad = float((out[name][1][:, ids] * d).sum())
+        say(f"64^3 {name}: adjoint {ad:.10e} central differences {fd[k]:.10e}")
+        assert abs(ad - fd[k]) <= 1e-5 * abs(fd[k])
+
+
+def test_autograd_eos_parameter_gradients():
+    """The torch wrapper returns gradients for A and Cv (and through the
+    final energies and densities): the mean pressure's autograd gradients
+    equal the library's adjoint plus the explicit terms."""
+    import torch
+    from paper_1707_04232_amd import sdpd
+    from paper_1707_04232_amd.autograd import sdpd_dynamics
+    say("autograd A, Cv gradients")
+    q, p, eps, ids = lattice_state(12, Cv=CV, T=1.0, jitter=0.1)
+    n = len(eps)
+    prm = sdpd.SdpdParams(n=n, box=(12.0, 12.0, 12.0), Cv=CV, fd=sdpd.FD_NONE)
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+    q0 = dev(q).requires_grad_()
+    A = torch.tensor(A0, dtype=torch.float64, device="cuda", requires_grad=True)
+    Cv = torch.tensor(CV, dtype=torch.float64, device="cuda", requires_grad=True)
+    qK, pK, eK, rK = sdpd_dynamics(q0, dev(p), dev(eps), prm, 8, 3, A=A, Cv=Cv, full=True)
+    J = (A * rK * eK / Cv).sum() / n
+    gq, gA, gC = torch.autograd.grad(J, (q0, A, Cv))
+    out = _gpu_obs_gradients(q, p, eps, ids.astype(np.int64), (12.0, 12.0, 12.0), 8, 3)["P"]
+    assert abs(J.item() - out[0]) <= 1e-12 * abs(out[0])
+    # the same cotangents up to the rounding of how the loss was written
+    assert np.abs(gq.cpu().numpy() - out[1]).max() <= 1e-12 * np.abs(out[1]).max()
+    assert abs(gA.item() - out[2]) <= 1e-12 * abs(out[2])
+    assert abs(gC.item() - out[3]) <= 1e-12 * max(abs(out[3]), 1e-12)
+    # the default A = Cv / (3 kB): the tie makes the dynamics independent of
+    # Cv, leaving only the explicit Cv dependence of J (none for the KE)
+    Cv2 = torch.tensor(CV, dtype=torch.float64, device="cuda", requires_grad=True)
+    qK, pK = sdpd_dynamics(dev(q), dev(p), dev(eps), prm, 8, 3, Cv=Cv2)
+    (gC2,) = torch.autograd.grad((pK * pK).sum() / 2, (Cv2,))
+    assert abs(gC2.item()) <= 1e-9
