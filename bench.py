@@ -69,26 +69,74 @@ def linear_slope(y):
     return float((x * (y - y.mean())).sum() / (x * x).sum())
 
 
-def cpu_baseline(w, sample_dims=(64, 64, 64), nsteps=2):
-    """The oracle as it stands: nsteps full steps of the same workload on a
-    sub-lattice of sample_dims (same density, heat capacity, temperature,
-    time step), single threaded (about 10 s)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(w, sample_dims=(64, 64, 64), nsteps=2, par_steps=3):
+    """The oracle as it stands, on the host of the GPU: its parallel step
+    variant (OpenMP, bit for bit the serial result) on the host's threads over
+    par_steps full steps of the workload itself, its single-threaded step on
+    nsteps steps of a sub-lattice of sample_dims (same density, heat
+    capacity, temperature, time step), and the small 10^3 case in full
+    (100 steps, one thread)."""
     import oracle as O
-    from paper_1707_04232_amd.workload import lattice_state
+    from paper_1707_04232_amd.workload import WORKLOADS, lattice_state, workload_state
+
+    def params(dims, ww):
+        return O.OracleParams(n=int(np.prod(dims)), box=tuple(float(d) for d in dims), Cv=ww.Cv,
+                              dt=ww.dt, eta=ww.eta, zeta=ww.zeta, h=ww.h, m=ww.m, kB=ww.kB,
+                              seed=ww.seed)
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    # parallel variant on the workload itself
+    q, p, eps, ids = workload_state(w)
+    P = params(w.dims, w)
+    S = O.State.from_arrays(q, p, eps, ids)
+    O.prepare(P, S)
+    t0 = time.perf_counter()
+    rc_par, _, used = O.step_parallel(P, S, 0, par_steps, threads=threads)
+    t_par = time.perf_counter() - t0
+    del S
+    # single thread on a sub-lattice
     q, p, eps, ids = lattice_state(sample_dims, Cv=w.Cv, T=w.T, seed=w.init_seed)
-    n = len(eps)
-    P = O.OracleParams(n=n, box=tuple(float(d) for d in sample_dims), Cv=w.Cv, dt=w.dt,
-                       eta=w.eta, zeta=w.zeta, h=w.h, m=w.m, kB=w.kB, seed=w.seed)
+    P = params(sample_dims, w)
     S = O.State.from_arrays(q, p, eps, ids)
     O.prepare(P, S)
     t0 = time.perf_counter()
     rc, _ = O.step(P, S, 0, nsteps)
-    dt = time.perf_counter() - t0
-    return {"value": n * nsteps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsteps} full steps (cells, density, EMS sweep, forces) of the same workload on a "
-                      f"{sample_dims[0]}x{sample_dims[1]}x{sample_dims[2]} sub-lattice "
-                      f"({n} particles), {dt:.1f} s, rc={rc}",
-            "cpu": platform.processor() or platform.machine()}
+    t_one = time.perf_counter() - t0
+    n_one = int(np.prod(sample_dims))
+    # the small case in full
+    c1 = WORKLOADS["lattice10_cv10"]
+    q, p, eps, ids = workload_state(c1)
+    P = params(c1.dims, c1)
+    S = O.State.from_arrays(q, p, eps, ids)
+    O.prepare(P, S)
+    t0 = time.perf_counter()
+    rc1, _ = O.step(P, S, 0, c1.steps)
+    t_c1 = time.perf_counter() - t0
+    return {"value": w.n * par_steps / t_par, "unit": "particle-steps/s", "cores": used,
+            "kind": "oracle",
+            "sample": f"{par_steps} full steps (cells, density, EMS sweep, forces) of the workload "
+                      f"itself ({w.n} particles) with the oracle's parallel step variant (OpenMP, "
+                      f"bit-identical to the single-threaded step) on {used} threads, "
+                      f"{t_par:.1f} s, rc={rc_par}",
+            "cpu": cpu_model(), "nproc": os.cpu_count(),
+            "single_thread": {"value": n_one * nsteps / t_one, "cores": 1,
+                              "sample": f"{nsteps} full steps of a {sample_dims[0]}x"
+                                        f"{sample_dims[1]}x{sample_dims[2]} sub-lattice "
+                                        f"({n_one} particles), {t_one:.1f} s, rc={rc}"},
+            "small_case_in_full": {"value": c1.n * c1.steps / t_c1, "cores": 1,
+                                   "sample": f"{c1.name}: {c1.n} particles, {c1.steps} steps, "
+                                             f"{t_c1:.1f} s, rc={rc1}"}}
 
 
 def replicas_bench(args):

@@ -10,7 +10,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .build import ensure_oracle
+from .build import ensure_oracle, ensure_oracle_omp
 
 KERNEL_LUCY, KERNEL_CUBIC = 0, 1
 FD_EMS, FD_AMS, FD_SSA, FD_NONE = 0, 1, 2, 3
@@ -77,58 +77,75 @@ def stats_dict(s: _Stats) -> dict:
 
 
 _lib = None
+_lib_omp = None
 _D = C.POINTER(C.c_double)
 _U32 = C.POINTER(C.c_uint32)
+
+
+def lib_omp():
+    """The OpenMP build of the same source (its so_step_parallel runs on
+    several threads)."""
+    global _lib_omp
+    if _lib_omp is None:
+        _lib_omp = _load(ensure_oracle_omp())
+    return _lib_omp
 
 
 def lib():
     global _lib
     if _lib is None:
-        L = C.CDLL(ensure_oracle())
-        PP, SP = C.POINTER(_Params), C.POINTER(_Stats)
-        sig = {
-            "so_kernel_w": (C.c_double, [C.c_int, C.c_double, C.c_double]),
-            "so_kernel_f": (C.c_double, [C.c_int, C.c_double, C.c_double]),
-            "so_entropy": (C.c_double, [PP, C.c_double, C.c_double]),
-            "so_temperature": (C.c_double, [PP, C.c_double, C.c_double]),
-            "so_pressure": (C.c_double, [PP, C.c_double, C.c_double]),
-            "so_heat_capacity": (C.c_double, [PP, C.c_double, C.c_double]),
-            "so_eps_at_entropy": (C.c_double, [PP, C.c_double, C.c_double]),
-            "so_grid": (C.c_int, [PP, C.POINTER(C.c_int32)]),
-            "so_build_cells": (C.c_int, [PP, _D, _D, _D, _D, _D, _U32, _U32]),
-            "so_density": (C.c_int, [PP, _D, _U32, _D]),
-            "so_density_bruteforce": (C.c_int, [PP, _D, _D]),
-            "so_update_eps_const_entropy": (C.c_int, [PP, _D, _D, _D]),
-            "so_forces": (C.c_int, [PP, _D, _D, _D, _U32, _D]),
-            "so_forces_bruteforce": (C.c_int, [PP, _D, _D, _D, _D]),
-            "so_philox4x32_10": (None, [_U32, _U32, _U32]),
-            "so_pair_draws": (None, [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
-                                     C.c_uint32, _D, _D]),
-            "so_fd_coefficients": (None, [PP, C.c_double, C.c_double, C.c_double,
-                                          C.c_double, C.c_double, C.c_double, _D, _D]),
-            "so_fd_log_ratio": (C.c_double, [PP, C.c_double, C.c_double, C.c_double,
-                                             C.c_double, C.c_double, _D, _D, _D, C.c_double,
-                                             _D, _D]),
-            "so_fd_pair_list": (C.c_int, [PP, _D, _U32, C.c_void_p, C.c_int64,
-                                          C.POINTER(C.c_int64)]),
-            "so_fd_sweep": (C.c_int, [PP, _D, _D, _D, _D, _U32, _U32, C.c_uint64,
-                                      C.c_double, SP, C.c_void_p, C.c_int64]),
-            "so_fd_sweep_flip": (C.c_int, [PP, _D, _D, _D, _D, _U32, _U32, C.c_uint64,
-                                           C.c_double, SP, C.c_void_p, C.c_int64,
-                                           C.POINTER(C.c_int64), C.POINTER(C.c_int32),
-                                           C.c_int64]),
-            "so_observe": (C.c_int, [PP, _D, _D, SP]),
-            "so_kick": (C.c_int, [PP, _D, _D, C.c_double]),
-            "so_drift": (C.c_int, [PP, _D, _D, C.c_double]),
-            "so_step": (C.c_int, [PP, _D, _D, _D, _D, _D, _U32, _U32, C.c_uint64,
-                                  C.c_int, SP]),
-        }
-        for name, (res, args) in sig.items():
-            fn = getattr(L, name)
-            fn.restype = res
-            fn.argtypes = args
-        _lib = L
+        _lib = _load(ensure_oracle())
     return _lib
+
+
+def _load(path):
+    L = C.CDLL(path)
+    PP, SP = C.POINTER(_Params), C.POINTER(_Stats)
+    sig = {
+        "so_kernel_w": (C.c_double, [C.c_int, C.c_double, C.c_double]),
+        "so_kernel_f": (C.c_double, [C.c_int, C.c_double, C.c_double]),
+        "so_entropy": (C.c_double, [PP, C.c_double, C.c_double]),
+        "so_temperature": (C.c_double, [PP, C.c_double, C.c_double]),
+        "so_pressure": (C.c_double, [PP, C.c_double, C.c_double]),
+        "so_heat_capacity": (C.c_double, [PP, C.c_double, C.c_double]),
+        "so_eps_at_entropy": (C.c_double, [PP, C.c_double, C.c_double]),
+        "so_grid": (C.c_int, [PP, C.POINTER(C.c_int32)]),
+        "so_build_cells": (C.c_int, [PP, _D, _D, _D, _D, _D, _U32, _U32]),
+        "so_density": (C.c_int, [PP, _D, _U32, _D]),
+        "so_density_bruteforce": (C.c_int, [PP, _D, _D]),
+        "so_update_eps_const_entropy": (C.c_int, [PP, _D, _D, _D]),
+        "so_forces": (C.c_int, [PP, _D, _D, _D, _U32, _D]),
+        "so_forces_bruteforce": (C.c_int, [PP, _D, _D, _D, _D]),
+        "so_philox4x32_10": (None, [_U32, _U32, _U32]),
+        "so_pair_draws": (None, [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
+                                 C.c_uint32, _D, _D]),
+        "so_fd_coefficients": (None, [PP, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, C.c_double, _D, _D]),
+        "so_fd_log_ratio": (C.c_double, [PP, C.c_double, C.c_double, C.c_double,
+                                         C.c_double, C.c_double, _D, _D, _D, C.c_double,
+                                         _D, _D]),
+        "so_fd_pair_list": (C.c_int, [PP, _D, _U32, C.c_void_p, C.c_int64,
+                                      C.POINTER(C.c_int64)]),
+        "so_fd_sweep": (C.c_int, [PP, _D, _D, _D, _D, _U32, _U32, C.c_uint64,
+                                  C.c_double, SP, C.c_void_p, C.c_int64]),
+        "so_fd_sweep_flip": (C.c_int, [PP, _D, _D, _D, _D, _U32, _U32, C.c_uint64,
+                                       C.c_double, SP, C.c_void_p, C.c_int64,
+                                       C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                       C.c_int64]),
+        "so_observe": (C.c_int, [PP, _D, _D, SP]),
+        "so_kick": (C.c_int, [PP, _D, _D, C.c_double]),
+        "so_drift": (C.c_int, [PP, _D, _D, C.c_double]),
+        "so_step": (C.c_int, [PP, _D, _D, _D, _D, _D, _U32, _U32, C.c_uint64,
+                              C.c_int, SP]),
+        "so_step_parallel": (C.c_int, [PP, _D, _D, _D, _D, _D, _U32, _U32, C.c_uint64,
+                                       C.c_int, SP]),
+        "so_threads": (C.c_int, [C.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
 
 
 def _d(a):
@@ -355,10 +372,25 @@ def drift(P, S: State, dt):
 
 def step(P, S: State, step0, nsteps):
     """nsteps full steps in place; returns (rc, list of per-step stats)."""
+    return _step(lib().so_step, P, S, step0, nsteps)
+
+
+def step_parallel(P, S: State, step0, nsteps, threads=0, omp=True):
+    """The parallel variant of step (the same result bit for bit): on
+    `threads` OpenMP threads (0 = the runtime's default) with the OpenMP
+    build, or on one thread with the plain build (omp=False).  Returns
+    (rc, per-step stats, threads used)."""
+    L = lib_omp() if omp else lib()
+    used = L.so_threads(int(threads))
+    rc, st = _step(L.so_step_parallel, P, S, step0, nsteps)
+    return rc, st, used
+
+
+def _step(fn, P, S, step0, nsteps):
     if S.cell_start is None:
         nc = grid(P)
         S.cell_start = np.zeros(nc[0] * nc[1] * nc[2] + 1, np.uint32)
     st = (_Stats * max(nsteps, 1))()
-    rc = lib().so_step(C.byref(P.c()), _d(S.q), _d(S.p), _d(S.eps), _d(S.rho), _d(S.f),
-                       _u(S.id), _u(S.cell_start), step0, nsteps, st)
+    rc = fn(C.byref(P.c()), _d(S.q), _d(S.p), _d(S.eps), _d(S.rho), _d(S.f), _u(S.id),
+            _u(S.cell_start), step0, nsteps, st)
     return rc, [stats_dict(st[k]) for k in range(nsteps)]

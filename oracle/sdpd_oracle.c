@@ -247,26 +247,30 @@ static double displacement(const so_params *P, const double *q, int64_t n,
 
 /* rho_i = sum_j m W(r_ij), all j with r_ij < h including j = i (A3).
  * Candidates come from the 27 cells around i's cell.                      */
+static double density_at(const so_params *P, const int32_t nc[3], const double *q,
+                         const uint32_t *cell_start, int64_t i)
+{
+    int64_t n = P->n;
+    double h2 = P->h * P->h;
+    int64_t c = cell_of(P, nc, q, n, i);
+    double rho = 0.0;
+    for (int k = 0; k < 27; ++k) {
+        int64_t c2 = cell_neighbour(nc, c, k);
+        for (int64_t j = cell_start[c2]; j < cell_start[c2 + 1]; ++j) {
+            double r[3];
+            double r2 = displacement(P, q, n, i, j, r);
+            if (r2 < h2) rho += P->m * so_kernel_w(P->kernel, P->h, sqrt(r2));
+        }
+    }
+    return rho;
+}
+
 int so_density(const so_params *P, const double *q, const uint32_t *cell_start,
                double *rho_out)
 {
     int32_t nc[3];
     if (so_grid(P, nc)) return SO_EINVAL;
-    int64_t n = P->n;
-    double h2 = P->h * P->h;
-    for (int64_t i = 0; i < n; ++i) {
-        int64_t c = cell_of(P, nc, q, n, i);
-        double rho = 0.0;
-        for (int k = 0; k < 27; ++k) {
-            int64_t c2 = cell_neighbour(nc, c, k);
-            for (int64_t j = cell_start[c2]; j < cell_start[c2 + 1]; ++j) {
-                double r[3];
-                double r2 = displacement(P, q, n, i, j, r);
-                if (r2 < h2) rho += P->m * so_kernel_w(P->kernel, P->h, sqrt(r2));
-            }
-        }
-        rho_out[i] = rho;
-    }
+    for (int64_t i = 0; i < P->n; ++i) rho_out[i] = density_at(P, nc, q, cell_start, i);
     return SO_OK;
 }
 
@@ -289,12 +293,18 @@ int so_density_bruteforce(const so_params *P, const double *q, double *rho_out)
 
 /* Sec. 3.1: along the conservative dynamics the entropies S_i are invariant,
  * so after the positions move eps_i = E(S_i, rho_i(q)).                    */
+static double eps_const_entropy(const so_params *P, double eps, double rho_old,
+                                double rho_new)
+{
+    double S = so_entropy(P, eps, rho_old);
+    return so_eps_at_entropy(P, S, rho_new);
+}
+
 int so_update_eps_const_entropy(const so_params *P, double *eps,
                                 const double *rho_old, const double *rho_new)
 {
     for (int64_t i = 0; i < P->n; ++i) {
-        double S = so_entropy(P, eps[i], rho_old[i]);
-        eps[i] = so_eps_at_entropy(P, S, rho_new[i]);
+        eps[i] = eps_const_entropy(P, eps[i], rho_old[i], rho_new[i]);
         if (!(eps[i] > 0.0) || !isfinite(eps[i])) return SO_ENONFINITE;
     }
     return SO_OK;
@@ -321,24 +331,29 @@ static void force_on(const so_params *P, const double *q, const double *rho,
     acc[2] += s * r[2];
 }
 
+static void force_at(const so_params *P, const int32_t nc[3], const double *q,
+                     const double *rho, const double *eps, const uint32_t *cell_start,
+                     int64_t i, double *f_out)
+{
+    int64_t n = P->n;
+    int64_t c = cell_of(P, nc, q, n, i);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 27; ++k) {
+        int64_t c2 = cell_neighbour(nc, c, k);
+        for (int64_t j = cell_start[c2]; j < cell_start[c2 + 1]; ++j)
+            if (j != i) force_on(P, q, rho, eps, i, j, acc);
+    }
+    f_out[i] = acc[0];
+    f_out[n + i] = acc[1];
+    f_out[2 * n + i] = acc[2];
+}
+
 int so_forces(const so_params *P, const double *q, const double *rho,
               const double *eps, const uint32_t *cell_start, double *f_out)
 {
     int32_t nc[3];
     if (so_grid(P, nc)) return SO_EINVAL;
-    int64_t n = P->n;
-    for (int64_t i = 0; i < n; ++i) {
-        int64_t c = cell_of(P, nc, q, n, i);
-        double acc[3] = {0.0, 0.0, 0.0};
-        for (int k = 0; k < 27; ++k) {
-            int64_t c2 = cell_neighbour(nc, c, k);
-            for (int64_t j = cell_start[c2]; j < cell_start[c2 + 1]; ++j)
-                if (j != i) force_on(P, q, rho, eps, i, j, acc);
-        }
-        f_out[i] = acc[0];
-        f_out[n + i] = acc[1];
-        f_out[2 * n + i] = acc[2];
-    }
+    for (int64_t i = 0; i < P->n; ++i) force_at(P, nc, q, rho, eps, cell_start, i, f_out);
     return SO_OK;
 }
 
@@ -780,6 +795,155 @@ int so_step(const so_params *P, double *q, double *p, double *eps, double *rho,
             rc = so_fd_sweep(P, q, p, eps, rho, id, cell_start, step, theta * P->dt, &st,
                              NULL, 0);
         so_forces(P, q, rho, eps, cell_start, f);
+        so_kick(P, p, f, 0.5 * P->dt);
+        so_observe(P, p, eps, &st);
+        if (per_step) per_step[s] = st;
+    }
+    free(rho_new);
+    return rc;
+}
+
+/* ======================================================================= */
+/* Parallel variant of the step (the CPU baseline on many cores)           */
+/* ======================================================================= */
+
+/* The same step as so_step with the independent work spread over OpenMP
+ * threads: density, energy update and forces per particle (each sum in the
+ * order above), and the F/D sweep phase by phase.  Inside one phase the
+ * tasks -- a cell (phase 0) or a cell pair (A, A + delta_o) -- share no
+ * particle (reading A12), so they run concurrently; each task applies its
+ * own pairs in (round, i) order, which is the order so_fd_sweep applies
+ * them in (its keys (phase, round, i) are distinct, and pairs of other
+ * tasks of the phase touch other particles).  The result is the serial one
+ * bit for bit.  Compiled without OpenMP it runs on one thread.            */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int so_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+static int cmp_roundkey(const void *a, const void *b)
+{
+    const pairkey *x = (const pairkey *)a, *y = (const pairkey *)b;
+    if (x->round != y->round) return x->round < y->round ? -1 : 1;
+    if (x->i != y->i) return x->i < y->i ? -1 : 1;
+    return 0;
+}
+
+/* the active pairs of task (A, offset k) in (round, i) order; returns the
+ * count (at most 64 * 64) */
+static int64_t task_pairs(const so_params *P, const int32_t nc[3], const double *q,
+                          const uint32_t *cell_start, int64_t A, int k, pairkey *out)
+{
+    int64_t n = P->n, cnt = 0;
+    double h2 = P->h * P->h;
+    int64_t B = cell_neighbour(nc, A, k);
+    for (int64_t i = cell_start[A]; i < cell_start[A + 1]; ++i) {
+        for (int64_t j = cell_start[B]; j < cell_start[B + 1]; ++j) {
+            if (k == 13 && j <= i) continue;
+            double r[3];
+            if (!(displacement(P, q, n, i, j, r) < h2)) continue;
+            out[cnt].phase = 0;
+            out[cnt].round = (int32_t)((i - cell_start[A]) ^ (j - cell_start[B]));
+            out[cnt].i = i;
+            out[cnt].j = j;
+            ++cnt;
+        }
+    }
+    qsort(out, (size_t)cnt, sizeof(pairkey), cmp_roundkey);
+    return cnt;
+}
+
+static int fd_sweep_parallel(const so_params *P, const double *q, double *p, double *eps,
+                             const double *rho, const uint32_t *id,
+                             const uint32_t *cell_start, uint64_t step, double dt_fd,
+                             so_stats *st)
+{
+    if (P->fd_mode == SO_FD_NONE) return SO_OK;
+    int32_t nc[3];
+    if (so_grid(P, nc)) return SO_EINVAL;
+    int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    uint64_t proposed = 0, rej_energy = 0, rej_ratio = 0, marginal = 0, negeps = 0;
+    int fail = 0;
+    for (int phase = 0; phase < 105; ++phase) {
+        int k = phase == 0 ? 13 : 14 + (phase - 1) / 8;
+        int par = phase == 0 ? -1 : (phase - 1) % 8;
+#pragma omp parallel reduction(+ : proposed, rej_energy, rej_ratio, marginal, negeps) \
+    reduction(| : fail)
+        {
+            pairkey *buf = (pairkey *)malloc(sizeof(pairkey) * 64 * 64);
+            so_stats ts;
+            memset(&ts, 0, sizeof ts);
+            if (!buf) fail = 1;
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t A = 0; A < ncell; ++A) {
+                if (!buf || (par >= 0 && cell_parity(nc, A) != par)) continue;
+                int64_t cnt = task_pairs(P, nc, q, cell_start, A, k, buf);
+                for (int64_t e = 0; e < cnt; ++e)
+                    fd_pair(P, q, p, eps, rho, id, buf[e].i, buf[e].j, step, dt_fd, &ts, NULL,
+                            0);
+            }
+            free(buf);
+            proposed += ts.proposed;
+            rej_energy += ts.rej_energy;
+            rej_ratio += ts.rej_ratio;
+            marginal += ts.marginal;
+            negeps += ts.negeps;
+        }
+    }
+    st->proposed += proposed;
+    st->rej_energy += rej_energy;
+    st->rej_ratio += rej_ratio;
+    st->marginal += marginal;
+    st->negeps += negeps;
+    if (fail) return SO_ENOMEM;
+    return st->negeps ? SO_ENEGEPS : SO_OK;
+}
+
+int so_step_parallel(const so_params *P, double *q, double *p, double *eps, double *rho,
+                     double *f, uint32_t *id, uint32_t *cell_start, uint64_t step0,
+                     int nsteps, so_stats *per_step)
+{
+    int32_t nc[3];
+    if (so_grid(P, nc)) return SO_EINVAL;
+    int64_t n = P->n;
+    int theta = P->fd_every > 0 ? P->fd_every : 1;
+    double *rho_new = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1));
+    if (!rho_new) return SO_ENOMEM;
+    int rc = SO_OK;
+    for (int s = 0; s < nsteps && rc == SO_OK; ++s) {
+        uint64_t step = step0 + (uint64_t)s;
+        so_stats st;
+        memset(&st, 0, sizeof st);
+        so_kick(P, p, f, 0.5 * P->dt);
+        so_drift(P, q, p, P->dt);
+        rc = so_build_cells(P, q, p, eps, rho, f, id, cell_start);
+        if (rc) break;
+        int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+        for (int64_t i = 0; i < n; ++i) {
+            rho_new[i] = density_at(P, nc, q, cell_start, i);
+            eps[i] = eps_const_entropy(P, eps[i], rho[i], rho_new[i]);
+            if (!(eps[i] > 0.0) || !isfinite(eps[i])) bad = 1;
+        }
+        memcpy(rho, rho_new, sizeof(double) * (size_t)n);
+        if (bad) {
+            rc = SO_ENONFINITE;
+            break;
+        }
+        if (step % (uint64_t)theta == 0)
+            rc = fd_sweep_parallel(P, q, p, eps, rho, id, cell_start, step, theta * P->dt, &st);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) force_at(P, nc, q, rho, eps, cell_start, i, f);
         so_kick(P, p, f, 0.5 * P->dt);
         so_observe(P, p, eps, &st);
         if (per_step) per_step[s] = st;

@@ -120,6 +120,16 @@ int so_step(const so_params *P, double *q, double *p, double *eps, double *rho,
             double *f, uint32_t *id, uint32_t *cell_start, uint64_t step0,
             int nsteps, so_stats *per_step);
 
+/* --- parallel variant (OpenMP; one thread when built without it) ------- */
+/* so_step with density, energy update and forces spread over threads per
+ * particle and the F/D sweep phase by phase over the phase's disjoint tasks
+ * (reading A12): the same result bit for bit.  so_threads sets the thread
+ * count (<= 0 keeps it) and returns the count in use.                      */
+int so_threads(int nthreads);
+int so_step_parallel(const so_params *P, double *q, double *p, double *eps, double *rho,
+                     double *f, uint32_t *id, uint32_t *cell_start, uint64_t step0,
+                     int nsteps, so_stats *per_step);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,10 @@
 //     quarter-turn rotation.
 //   * sqrt: reciprocal square root estimate with two Newton steps, one
 //     Newton correction of the product.
+//   * expm1: x = k ln 2 + r with |r| <= ln 2 / 2 (two-part ln 2), the Taylor
+//     polynomial of expm1(r) to degree 13 (its tail is below 2^-53 |r|), and
+//     expm1(x) = 2^k expm1(r) + (2^k - 1) in one fused step; for |x| <= ln 2 / 2
+//     k = 0 and the polynomial alone is the result.
 #pragma once
 
 namespace sdpd {
@@ -45,6 +49,28 @@ __device__ __forceinline__ double fd_sqrt(double x)
     const double y = fast_rsq(x);
     const double s = x * y;
     return fma(0.5 * y, fma(-s, s, x), s);
+}
+
+// expm1(x) for finite x with |x| < 700
+__device__ __forceinline__ double fd_expm1(double x)
+{
+    const double k = rint(x * 1.4426950408889634);
+    const double r = fma(-k, 1.9082149292705877e-10, fma(-k, 0.6931471803691238, x));
+    double p = 1.6059043836821613e-10;   // 1/13!
+    p = fma(p, r, 2.08767569878681e-09);   // 1/12!
+    p = fma(p, r, 2.505210838544172e-08);  // 1/11!
+    p = fma(p, r, 2.755731922398589e-07);  // 1/10!
+    p = fma(p, r, 2.7557319223985893e-06); // 1/9!
+    p = fma(p, r, 2.48015873015873e-05);   // 1/8!
+    p = fma(p, r, 0.0001984126984126984);  // 1/7!
+    p = fma(p, r, 0.001388888888888889);   // 1/6!
+    p = fma(p, r, 0.008333333333333333);   // 1/5!
+    p = fma(p, r, 0.041666666666666664);   // 1/4!
+    p = fma(p, r, 0.16666666666666666);    // 1/3!
+    p = fma(p, r, 0.5);
+    p = fma(p * r, r, r);                  // r + r^2 (1/2 + r/6 + ...)
+    const double t = ldexp(1.0, (int)k);
+    return fma(t, p, t - 1.0);
 }
 
 __device__ __forceinline__ double fd_log(double x)

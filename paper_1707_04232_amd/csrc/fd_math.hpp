@@ -81,8 +81,8 @@ __device__ __forceinline__ Coef fd_coef(const DevParams &P, double kpar, double 
     const double d = P.kB * Tred * inv_Ts * P.two_over_Cv;
     const double omd = 1.0 - d;
     const double c = -2.0 * dt * P.inv_m * omd;
-    const double e_perp = expm1(c * kperp);
-    const double e_par = (FAST || P.par_twice_perp) ? e_perp * (2.0 + e_perp) : expm1(c * kpar);
+    const double e_perp = fd_expm1(c * kperp);
+    const double e_par = (FAST || P.par_twice_perp) ? e_perp * (2.0 + e_perp) : fd_expm1(c * kpar);
     const double s = P.b2_c * Tred * fast_rcp(omd);
     Coef r;
     r.al_par = 1.0 + e_par;
@@ -196,13 +196,15 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
             const double wqx = vqx - g.al_perp * nqx;
             const double wqy = vqy - g.al_perp * nqy;
             const double wqz = vqz - g.al_perp * nqz;
-            const double quad = wpar * wpar * fast_rcp(g.b2_par)
-                                + (wqx * wqx + wqy * wqy + wqz * wqz) * fast_rcp(g.b2_perp);
+            // one reciprocal serves both inverse variances and the determinant
+            // ratio: inv = 1/(b'_par^2 b'_perp^2)
+            const double inv = fast_rcp(g.b2_par * g.b2_perp);
+            const double quad = wpar * wpar * (g.b2_perp * inv)
+                                + (wqx * wqx + wqy * wqy + wqz * wqz) * (g.b2_par * inv);
             const double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
             const double A = 0.5 * G2 - 0.5 * quad;
             // log|B(v)| - log|B(v')| = (1/2) log Dr, Dr = b_par^2 b_perp^4 / (b'_par^2 b'_perp^4)
-            const double Dr = (f.b2_par * f.b2_perp * f.b2_perp)
-                              * fast_rcp(g.b2_par * g.b2_perp * g.b2_perp);
+            const double Dr = (f.b2_par * f.b2_perp * f.b2_perp) * (g.b2_par * (inv * inv));
             // ideal gas: sum_k (S(eps'_k) - S(eps_k))/kB - log T(eps'_k) + log T(eps_k)
             //          = (Cv/kB - 1) log(1 + w), 1 + w = (1 - delta/ei)(1 - delta/ej)
             const double inv_eiej = fast_rcp(ei * ej);
