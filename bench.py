@@ -141,10 +141,12 @@ def cpu_baseline(w, sample_dims=(64, 64, 64), nsteps=2, par_steps=3):
 
 def replicas_bench(args):
     """Batched replicas: 256 boxes of uneven size and state, each a context of
-    its own, spread over args.streams streams and advanced by captured HIP
-    graphs (one per stream when the process has a hardware queue per
-    stream); compared with launching every box's step from the host in
-    turn."""
+    its own, advanced together by the library's batch: by default every stage
+    of a step is one launch for all boxes (--batch-layout fused); with
+    --batch-layout graphs each box's launches are captured into a graph per
+    stream (args.streams streams, a hardware queue per stream).  Compared
+    with launching every box's step from the host in turn.  --prec mixed
+    runs the density and force passes in FP32 (the F/D update stays FP64)."""
     import torch
     from paper_1707_04232_amd import sdpd
     from paper_1707_04232_amd.workload import lattice_state, replica_set
@@ -154,7 +156,8 @@ def replicas_bench(args):
     ctxs, states, n_tot = [], [], 0
     for b, (side, T, Cv) in enumerate(boxes):
         q, p, eps, ids = lattice_state(side, Cv=Cv, T=T, seed=b)
-        prm = sdpd.SdpdParams(n=len(eps), box=float(side), Cv=Cv, replica=b)
+        prm = sdpd.SdpdParams(n=len(eps), box=float(side), Cv=Cv, replica=b,
+                              prec=sdpd.MIXED if args.prec == "mixed" else sdpd.FP64)
         S = sdpd.DeviceState.from_numpy(q, p, eps, ids)
         with torch.cuda.stream(streams[b % len(streams)]):
             ctx = sdpd.Context(prm)
@@ -166,7 +169,17 @@ def replicas_bench(args):
     print(f"# replicas: {nbox} boxes, {n_tot} particles, sides {min(b[0] for b in boxes)}.."
           f"{max(b[0] for b in boxes)}", file=sys.stderr, flush=True)
     tuned = None
-    if args.autotune:
+    if args.tasks:
+        tt = tuple(int(x) for x in args.tasks.split(","))
+        for ctx in ctxs:   # LDS capacities as the defaults give these task counts
+            ctx.tune(tt, (-1,) * 4, (-1,) * 4)
+            if args.lds_scale != 1.0:
+                t = ctx.get_tuning()
+                ctx.tune(tt, [max(128, int(x * args.lds_scale) // 16 * 16)
+                              for x in t["lds_particles"]],
+                         [max(64, int(x * args.lds_scale) // 64 * 64) for x in t["lds_pairs"]])
+        tuned = {"fd_tasks": {"all": tt}, "seconds": 0.0}
+    elif args.autotune:
         # the library's autotuner on the largest box of each size class (sides
         # in bands of 7 sites); its tuning is then given to every box of the class
         t0 = time.perf_counter()
@@ -184,7 +197,8 @@ def replicas_bench(args):
         tuned = {"fd_tasks": tuned, "seconds": time.perf_counter() - t0}
         print(f"# autotuned {tuned}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    B = sdpd.Batch(ctxs, states)
+    B = sdpd.Batch(ctxs, states, layout=sdpd.BATCH_FUSED if args.batch_layout == "fused"
+                   else sdpd.BATCH_GRAPHS, parts=args.batch_parts)
     t_capture = time.perf_counter() - t0
     B.run(0, args.warmup)
     torch.cuda.synchronize()
@@ -195,6 +209,11 @@ def replicas_bench(args):
     for c in ctxs:
         c.sync()
     E = [c.observe(S)["E"] for c, S in zip(ctxs, states)]
+    # energy drift of the batch over the timed steps: each box's E observed
+    # once more after a short further run (no per-step records in a batch)
+    B.run(args.warmup + args.steps, 10)
+    torch.cuda.synchronize()
+    E10 = [c.observe(S)["E"] for c, S in zip(ctxs, states)]
     # the same boxes stepped eagerly, box after box, from the host
     k0 = args.warmup + args.steps
     neager = max(2, min(20, args.steps // 10))
@@ -210,22 +229,26 @@ def replicas_bench(args):
         c.close()
     value = n_tot * args.steps / el
     out = {
-        "metric": "particle-steps/s (full SDPD step), 256 replica boxes in captured HIP graphs",
+        "metric": "particle-steps/s (full SDPD step), 256 replica boxes in one batch",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "replicas256", "boxes": nbox, "n_total": n_tot,
                    "sides": [min(b[0] for b in boxes), max(b[0] for b in boxes)],
                    "T_range": [0.1, 2.0], "Cv_range": [1.5, 50.0], "streams": len(streams),
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
-                   "dt": 0.005, "fd": "EMS"},
+                   "dt": 0.005, "fd": "EMS", "prec": args.prec,
+                   "batch_layout": args.batch_layout, "batch_parts": args.batch_parts},
         "eager_sequential": {"value": n_tot * neager / el_eager, "steps": neager,
                              "ms_per_step": 1e3 * el_eager / neager},
         "graph_speedup": (n_tot * args.steps / el) / (n_tot * neager / el_eager),
         "capture_s": t_capture,
         "autotune": tuned,
         "sum_E_final": float(np.sum(E)),
+        "sum_E_after_10_more_steps": float(np.sum(E10)),
+        "relative_energy_change_10_steps": float(abs(np.sum(E10) - np.sum(E)) / abs(np.sum(E))),
     }
     print(json.dumps(out), flush=True)
 
@@ -338,6 +361,17 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="replicas workload: keep the default tuning instead of running the "
                          "library's autotuner per box size class")
+    ap.add_argument("--batch-layout", choices=("fused", "graphs"), default="fused",
+                    help="replicas workload: one launch per stage for all boxes (fused), or "
+                         "each box's launches captured into graphs per stream (graphs)")
+    ap.add_argument("--tasks", default="",
+                    help="replicas workload: tasks per workgroup of the four F/D phase classes "
+                         "for every box, e.g. 4,4,8,12 (instead of the autotuner)")
+    ap.add_argument("--lds-scale", type=float, default=1.0,
+                    help="replicas workload with --tasks: scale of the LDS capacities")
+    ap.add_argument("--batch-parts", type=int, default=0,
+                    help="replicas workload, fused layout: parts of the batch, each on its own "
+                         "stream (0 = the library's choice)")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket kernels with HIP events")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,

@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SDPD_ABI_VERSION 6
+#define SDPD_ABI_VERSION 7
 
 typedef enum {
     SDPD_OK = 0,
@@ -228,8 +228,9 @@ int sdpd_timing(sdpd_ctx *ctx, double ms[6], int64_t launches[6]);
  * A workgroup whose tasks need more than its capacity processes them in
  * several batches.  The LDS of one workgroup, 36 B per particle + 4 B per
  * pair entry + 1320 B, must fit the device's per-workgroup limit.  Fields
- * equal to 0 in sdpd_tune keep the current value (sdpd_tune waits for the
- * context's stream first); sdpd_get_tuning reports
+ * equal to 0 in sdpd_tune keep the current value, and a negative LDS field
+ * selects the capacities the defaults give the class's (new) task count
+ * (sdpd_tune waits for the context's stream first); sdpd_get_tuning reports
  * the values in use (the defaults scale with the mean particles per cell).
  * SDPD_EINVAL for out-of-range values; nothing is changed then.          */
 typedef struct {
@@ -281,9 +282,10 @@ int sdpd_autotune(sdpd_ctx *ctx, const sdpd_state *state, int trials, sdpd_tunin
  * use created streams (not the null stream, which cannot be captured).
  * sdpd_batch_create captures fd_every consecutive steps of every box into
  * HIP graphs (it waits for the boxes' streams first; the graphs refer to
- * the given state arrays, which must stay allocated): one graph per stream
- * when the process has at least as many hardware queues as there are
- * streams (environment GPU_MAX_HW_QUEUES, 4 when unset), else one graph
+ * the given state arrays, which must stay allocated) in the fused layout of
+ * sdpd_batch_create_layout below.  In the graph layout: one graph per
+ * stream when the process has at least as many hardware queues as there
+ * are streams (environment GPU_MAX_HW_QUEUES, 4 when unset), else one graph
  * that forks to and joins the boxes' streams.  sdpd_batch_run
  * replays it for steps step0 .. step0+nsteps-1 (both multiples of
  * fd_every; SDPD_EINVAL if a context was retuned with sdpd_tune after the
@@ -295,6 +297,27 @@ int sdpd_autotune(sdpd_ctx *ctx, const sdpd_state *state, int trials, sdpd_tunin
 typedef struct sdpd_batch sdpd_batch;
 int sdpd_batch_create(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
                       sdpd_batch **out);
+
+/* The same with an explicit layout:
+ *   SDPD_BATCH_FUSED   every stage of the step runs for all boxes in one
+ *                      launch (each box's workgroups and arguments as in its
+ *                      own step, taken from device tables), the launches of
+ *                      fd_every steps captured in a graph; the boxes are
+ *                      dealt into `parts` parts of about equal particle
+ *                      count (<= 0: min(GPU_MAX_HW_QUEUES, 16)), each with
+ *                      its own graph and stream, which run side by side;
+ *                      ~50 launches per part and step for any number of
+ *                      boxes.  Boxes of any size, precision and scheme.
+ *   SDPD_BATCH_GRAPHS  each box's own launch sequence captured: one graph per
+ *                      stream, or one graph forking to the boxes' streams
+ *                      (see sdpd_batch_create above);
+ *   SDPD_BATCH_AUTO    the fused layout (what sdpd_batch_create uses).
+ * Results are identical bit for bit in every layout.  sdpd_batch_layout
+ * returns the layout in use (SDPD_EINVAL for NULL).                         */
+enum { SDPD_BATCH_AUTO = 0, SDPD_BATCH_FUSED = 1, SDPD_BATCH_GRAPHS = 2 };
+int sdpd_batch_create_layout(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
+                             int layout, int parts, sdpd_batch **out);
+int sdpd_batch_layout(const sdpd_batch *batch);
 int sdpd_batch_run(sdpd_batch *batch, uint64_t step0, int nsteps);
 int sdpd_batch_destroy(sdpd_batch *batch);
 

@@ -579,6 +579,12 @@ int sdpd_tune(sdpd_ctx *c, const sdpd_tuning *t)
     sdpd_tuning u = c->tuning;
     for (int k = 0; k < 4; ++k) {
         if (t->fd_tasks[k]) u.fd_tasks[k] = t->fd_tasks[k];
+        if (t->fd_lds_particles[k] < 0 || t->fd_lds_pairs[k] < 0) {
+            // the capacities the defaults give this many tasks
+            if (u.fd_tasks[k] < 1 || u.fd_tasks[k] > FD_MAXTASKS) return SDPD_EINVAL;
+            fd_class_caps(c, k, u.fd_tasks[k], u.fd_lds_particles[k], u.fd_lds_pairs[k]);
+            continue;
+        }
         if (t->fd_lds_particles[k]) u.fd_lds_particles[k] = t->fd_lds_particles[k];
         if (t->fd_lds_pairs[k]) u.fd_lds_pairs[k] = t->fd_lds_pairs[k];
     }

@@ -1,7 +1,23 @@
 // Batched replicas: many independent boxes (each its own context and
 // stream) advanced together by HIP graphs holding fd_every consecutive steps
-// of every box, captured once from the same launch sequence the eager
-// sdpd_step issues.  Two layouts:
+// of every box.
+//
+// Fused layout (the default): every stage of the step runs for all boxes in
+// one launch.  Each box's contexts records the launches its eager step would
+// issue (kernel, grid, LDS, argument struct); position k of every box's
+// sequence becomes one multi-box launch per distinct kernel at that position,
+// whose workgroups are the boxes' workgroups, each reading its box's
+// argument struct from a device table.  A box's launches stay in their order
+// and keep their grids, so each box computes exactly what its eager step
+// computes, bit for bit; a step of 256 boxes is ~50 launches instead of
+// ~13,000.  The boxes are dealt into a few parts of about equal particle
+// count (largest first); each part's launch sequence for fd_every steps is
+// captured in a graph of its own on a stream of its own, so that one part's
+// launches fill the GPU while another's drain (the launch of a sweep group
+// ends with its slowest task range).
+//
+// Graph layouts (the previous one, selectable): the launch sequence of
+// each box captured as it is:
 //   * one graph per stream (the boxes of that stream, replayed on it), when
 //     the process has a hardware queue for every stream (GPU_MAX_HW_QUEUES,
 //     4 unless set): the streams then run side by side;
@@ -21,7 +37,33 @@
 
 #include "sdpd_internal.hpp"
 
+namespace {
+
+// one multi-box launch of the fused layout
+struct FusedLaunch {
+    sdpd::MultiKernel multi = nullptr;
+    unsigned block = 0, nblocks = 0;
+    size_t lds = 0;
+    void *tab = nullptr;   // device: argument structs of the participating boxes
+    uint2 *wg = nullptr;   // device: (slot in tab, workgroup of that box)
+};
+
+// boxes advanced by one sequence of multi-box launches on one stream
+struct FusedPart {
+    std::vector<int> boxes;
+    std::vector<FusedLaunch> launches;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+};
+
+}  // namespace
+
 struct sdpd_batch {
+    int layout = SDPD_BATCH_GRAPHS;
+    std::vector<FusedPart> parts;
+    unsigned long long **dsteps = nullptr;   // device: each box's step-index word
     std::vector<sdpd_ctx *> ctx;
     std::vector<sdpd_state> st;
     std::vector<int> gen;               // the contexts' tuning at capture
@@ -50,6 +92,18 @@ static void batch_free(sdpd_batch *b)
 {
     if (b->origin) (void)hipStreamSynchronize(b->origin);
     for (hipStream_t st : b->streams) (void)hipStreamSynchronize(st);
+    for (FusedPart &p : b->parts) {
+        if (p.stream) (void)hipStreamSynchronize(p.stream);
+        for (FusedLaunch &f : p.launches) {
+            if (f.tab) (void)hipFree(f.tab);
+            if (f.wg) (void)hipFree(f.wg);
+        }
+        if (p.exec) (void)hipGraphExecDestroy(p.exec);
+        if (p.graph) (void)hipGraphDestroy(p.graph);
+        if (p.done) (void)hipEventDestroy(p.done);
+        if (p.stream) (void)hipStreamDestroy(p.stream);
+    }
+    if (b->dsteps) (void)hipFree(b->dsteps);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (hipGraphExec_t e : b->sexec)
@@ -66,13 +120,132 @@ static void batch_free(sdpd_batch *b)
     delete b;
 }
 
+// every box's step-index word set to v (one launch)
+__global__ void k_set_steps(unsigned long long *const *dsteps, int nbox, unsigned long long v)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < nbox) *dsteps[i] = v;
+}
+
+// Record theta steps of every box, deal the boxes into parts and merge each
+// part's records into multi-box launches (see the header of this file).
+static int build_fused(sdpd_batch *b, int nparts)
+{
+    const int nbox = (int)b->ctx.size();
+    std::vector<LaunchRecord> recs(nbox);
+    int rc = SDPD_OK;
+    for (int i = 0; i < nbox && !rc; ++i) {
+        sdpd_ctx *c = b->ctx[i];
+        c->rec = &recs[i];
+        c->fd_per_group = 1;
+        for (int k = 0; k < b->theta && !rc; ++k) rc = enqueue_step(c, &b->st[i], (uint64_t)k, false);
+        c->fd_per_group = 0;
+        c->rec = nullptr;
+    }
+    if (rc) return rc;
+    // parts of about equal particle count: largest box first to the lightest part
+    nparts = std::max(1, std::min(nparts, nbox));
+    std::vector<int> order(nbox);
+    for (int i = 0; i < nbox; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return b->ctx[x]->n > b->ctx[y]->n; });
+    b->parts.resize(nparts);
+    std::vector<int64_t> load(nparts, 0);
+    for (int i : order) {
+        const int p = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        b->parts[p].boxes.push_back(i);
+        load[p] += std::max<int64_t>(b->ctx[i]->n, 1);
+    }
+    for (FusedPart &part : b->parts) {
+        std::sort(part.boxes.begin(), part.boxes.end());
+        size_t maxlen = 0;
+        for (int i : part.boxes) maxlen = std::max(maxlen, recs[i].size());
+        for (size_t pos = 0; pos < maxlen; ++pos) {
+            // boxes with the same kernel at this position share one launch
+            std::vector<MultiKernel> kinds;
+            for (int i : part.boxes)
+                if (pos < recs[i].size() &&
+                    std::find(kinds.begin(), kinds.end(), recs[i][pos].multi) == kinds.end())
+                    kinds.push_back(recs[i][pos].multi);
+            for (MultiKernel kind : kinds) {
+                FusedLaunch f;
+                f.multi = kind;
+                std::vector<unsigned char> tab;
+                std::vector<uint2> wg;
+                unsigned slot = 0;
+                for (int i : part.boxes) {
+                    if (pos >= recs[i].size() || recs[i][pos].multi != kind) continue;
+                    const RecordedLaunch &r = recs[i][pos];
+                    if (f.block && r.block != f.block) return SDPD_EINVAL;
+                    f.block = r.block;
+                    f.lds = std::max(f.lds, r.lds);
+                    tab.insert(tab.end(), r.args.begin(), r.args.end());
+                    for (unsigned blk = 0; blk < r.grid; ++blk) wg.push_back(make_uint2(slot, blk));
+                    ++slot;
+                }
+                if (wg.empty()) continue;
+                if (wg.size() > 0x7fffffffull) return SDPD_EINVAL;
+                f.nblocks = (unsigned)wg.size();
+                part.launches.push_back(f);   // freed with the batch from here on
+                FusedLaunch &g = part.launches.back();
+                if (hipMalloc(&g.tab, tab.size()) != hipSuccess) return SDPD_ENOMEM;
+                if (hipMalloc((void **)&g.wg, sizeof(uint2) * wg.size()) != hipSuccess)
+                    return SDPD_ENOMEM;
+                if ((rc = check_hip(hipMemcpy(g.tab, tab.data(), tab.size(),
+                                              hipMemcpyHostToDevice))) ||
+                    (rc = check_hip(hipMemcpy(g.wg, wg.data(), sizeof(uint2) * wg.size(),
+                                              hipMemcpyHostToDevice))))
+                    return rc;
+            }
+        }
+    }
+    std::vector<unsigned long long *> ds(nbox);
+    for (int i = 0; i < nbox; ++i) ds[i] = (unsigned long long *)b->ctx[i]->dstep;
+    if (hipMalloc((void **)&b->dsteps, sizeof(void *) * nbox) != hipSuccess) return SDPD_ENOMEM;
+    return check_hip(hipMemcpy(b->dsteps, ds.data(), sizeof(void *) * nbox, hipMemcpyHostToDevice));
+}
+
+// capture each part's fused launches of theta steps into a graph on its stream
+static int capture_fused(sdpd_batch *b)
+{
+    for (FusedPart &part : b->parts) {
+        if (hipStreamCreateWithFlags(&part.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&part.done, hipEventDisableTiming) != hipSuccess)
+            return SDPD_EHIP;
+        if (hipStreamBeginCapture(part.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return SDPD_EHIP;
+        for (const FusedLaunch &f : part.launches)
+            hipLaunchKernelGGL(f.multi, dim3(f.nblocks), dim3(f.block), f.lds, part.stream,
+                               (const void *)f.tab, (const uint2 *)f.wg);
+        int rc = check_hip(hipGetLastError());
+        const hipError_t ec = hipStreamEndCapture(part.stream, &part.graph);
+        if (!rc && ec != hipSuccess) rc = SDPD_EHIP;
+        if (!rc && hipGraphInstantiate(&part.exec, part.graph, nullptr, nullptr, 0) != hipSuccess)
+            rc = SDPD_EHIP;
+        if (rc) return rc;
+    }
+    return SDPD_OK;
+}
+
 extern "C" {
 
 int sdpd_batch_create(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
                       sdpd_batch **out)
 {
+    return sdpd_batch_create_layout(ctxs, states, nbox, SDPD_BATCH_AUTO, 0, out);
+}
+
+int sdpd_batch_layout(const sdpd_batch *b)
+{
+    return b ? b->layout : SDPD_EINVAL;
+}
+
+int sdpd_batch_create_layout(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
+                             int layout, int parts, sdpd_batch **out)
+{
     if (!out || !ctxs || !states || nbox < 1) return SDPD_EINVAL;
     *out = nullptr;
+    if (layout < SDPD_BATCH_AUTO || layout > SDPD_BATCH_GRAPHS) return SDPD_EINVAL;
     const int theta = ctxs[0] ? ctxs[0]->prm.fd_every : 0;
     for (int k = 0; k < nbox; ++k) {
         const sdpd_ctx *c = ctxs[k];
@@ -112,6 +285,18 @@ int sdpd_batch_create(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
     if (rc) {
         batch_free(b);
         return rc;
+    }
+    if (layout != SDPD_BATCH_GRAPHS) {
+        b->layout = SDPD_BATCH_FUSED;
+        rc = build_fused(b, parts > 0 ? parts : std::min(hw_queues(), 16));
+        if (!rc) rc = capture_fused(b);
+        if (rc) {
+            (void)hipGetLastError();
+            batch_free(b);
+            return rc;
+        }
+        *out = b;
+        return SDPD_OK;
     }
     if (b->streams.size() > 1 && (int)b->streams.size() <= hw_queues()) {
         // per-stream graphs: each stream captures theta steps of its boxes
@@ -186,6 +371,29 @@ int sdpd_batch_run(sdpd_batch *b, uint64_t step0, int nsteps)
         if (b->ctx[k]->tune_gen != b->gen[k]) return SDPD_EINVAL;   // retuned since the capture
     if (nsteps == 0) return SDPD_OK;
     int rc;
+    if (b->layout == SDPD_BATCH_FUSED) {
+        // the boxes' earlier work first, then everything on the batch's stream
+        for (size_t i = 0; i < b->streams.size(); ++i) {
+            if ((rc = check_hip(hipEventRecord(b->ready[i], b->streams[i])))) return rc;
+            if ((rc = check_hip(hipStreamWaitEvent(b->origin, b->ready[i], 0)))) return rc;
+        }
+        const int nbox = (int)b->ctx.size();
+        hipLaunchKernelGGL(k_set_steps, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0,
+                           b->origin, b->dsteps, nbox, (unsigned long long)step0);
+        if ((rc = check_hip(hipGetLastError()))) return rc;
+        if ((rc = check_hip(hipEventRecord(b->fork, b->origin)))) return rc;
+        for (FusedPart &part : b->parts) {
+            if ((rc = check_hip(hipStreamWaitEvent(part.stream, b->fork, 0)))) return rc;
+            for (int r = 0; r < nsteps / b->theta; ++r)
+                if ((rc = check_hip(hipGraphLaunch(part.exec, part.stream)))) return rc;
+            if ((rc = check_hip(hipEventRecord(part.done, part.stream)))) return rc;
+            if ((rc = check_hip(hipStreamWaitEvent(b->origin, part.done, 0)))) return rc;
+        }
+        if ((rc = check_hip(hipEventRecord(b->done, b->origin)))) return rc;
+        for (hipStream_t s : b->streams)
+            if ((rc = check_hip(hipStreamWaitEvent(s, b->done, 0)))) return rc;
+        return SDPD_OK;
+    }
     for (sdpd_ctx *c : b->ctx)
         if ((rc = launch_fill_u64(c, (unsigned long long *)c->dstep, step0, 1))) return rc;
     if (!b->sexec.empty()) {

@@ -7,17 +7,31 @@
 
 namespace sdpd {
 
-__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
+struct FillU32Args {
+    uint32_t *p;
+    uint32_t v;
+    int64_t n;
+};
+__device__ __forceinline__ void fill_u32_body(const FillU32Args &a, uint32_t blk)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
+    if (i < a.n) a.p[i] = a.v;
 }
+__global__ void k_fill_u32(FillU32Args a) { fill_u32_body(a, blockIdx.x); }
+SDPD_MULTI_KERNEL(k_fill_u32_multi, FillU32Args, fill_u32_body, 256)
 
-__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n)
+struct FillU64Args {
+    unsigned long long *p;
+    unsigned long long v;
+    int64_t n;
+};
+__device__ __forceinline__ void fill_u64_body(const FillU64Args &a, uint32_t blk)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
+    if (i < a.n) a.p[i] = a.v;
 }
+__global__ void k_fill_u64(FillU64Args a) { fill_u64_body(a, blockIdx.x); }
+SDPD_MULTI_KERNEL(k_fill_u64_multi, FillU64Args, fill_u64_body, 256)
 
 // Half kick and drift of the Velocity-Verlet scheme, eq. (sdpd-verlet),
 // fused with the cell assignment:  p += dt/2 f;  q += dt p / m wrapped once
@@ -44,11 +58,21 @@ __device__ __forceinline__ uint32_t wave_counted_inc(uint32_t *ctr, uint32_t key
     return pos;
 }
 
-__global__ void k_kick_drift_assign(DevParams P, double *q, double *p, const double *f,
-                                    int kick_drift, uint32_t *cell_of, uint32_t *count,
-                                    uint32_t *err)
+struct KickDriftArgs {
+    DevParams P;
+    double *q, *p;
+    const double *f;
+    int kick_drift;
+    uint32_t *cell_of, *count, *err;
+};
+__device__ __forceinline__ void kick_drift_assign_body(const KickDriftArgs &a, uint32_t blk)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const DevParams &P = a.P;
+    double *q = a.q, *p = a.p;
+    const double *f = a.f;
+    const int kick_drift = a.kick_drift;
+    uint32_t *cell_of = a.cell_of, *count = a.count, *err = a.err;
+    int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
     const int64_t n = P.n;
     int cc[3];
@@ -72,6 +96,8 @@ __global__ void k_kick_drift_assign(DevParams P, double *q, double *p, const dou
     cell_of[i] = c;
     (void)wave_counted_inc(count, c);
 }
+__global__ void k_kick_drift_assign(KickDriftArgs a) { kick_drift_assign_body(a, blockIdx.x); }
+SDPD_MULTI_KERNEL(k_kick_drift_assign_multi, KickDriftArgs, kick_drift_assign_body, 256)
 
 // --- exclusive scan of the cell counts into cell_start (3 passes) ---------
 constexpr int SCAN_THREADS = 256;
@@ -95,11 +121,20 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s, uint32_t *tota
     return incl - v;
 }
 
-__global__ void k_scan_local(const uint32_t *count, int64_t ncell, int cap, uint32_t *out,
-                             uint32_t *block_sums, uint32_t *err)
+struct ScanLocalArgs {
+    const uint32_t *count;
+    int64_t ncell;
+    int cap;
+    uint32_t *out, *block_sums, *err;
+};
+__device__ __forceinline__ void scan_local_body(const ScanLocalArgs &a, uint32_t blk)
 {
+    const uint32_t *count = a.count;
+    const int64_t ncell = a.ncell;
+    const int cap = a.cap;
+    uint32_t *out = a.out, *block_sums = a.block_sums, *err = a.err;
     __shared__ uint32_t s[SCAN_THREADS];
-    int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_PER_THREAD;
+    int64_t base = (int64_t)blk * SCAN_BLOCK + threadIdx.x * SCAN_PER_THREAD;
     uint32_t v[SCAN_PER_THREAD], sum = 0;
     bool over = false;
 #pragma unroll
@@ -116,13 +151,24 @@ __global__ void k_scan_local(const uint32_t *count, int64_t ncell, int cap, uint
         if (base + k < ncell) out[base + k] = ex;
         ex += v[k];
     }
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+    if (threadIdx.x == 0) block_sums[blk] = total;
 }
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_local(ScanLocalArgs a)
+{
+    scan_local_body(a, blockIdx.x);
+}
+SDPD_MULTI_KERNEL(k_scan_local_multi, ScanLocalArgs, scan_local_body, SCAN_THREADS)
 
 // one workgroup: exclusive scan of the block sums, in place; the grand
 // total goes to block_sums[nblocks]
-__global__ void k_scan_sums(uint32_t *block_sums, int64_t nblocks)
+struct ScanSumsArgs {
+    uint32_t *block_sums;
+    int64_t nblocks;
+};
+__device__ __forceinline__ void scan_sums_body(const ScanSumsArgs &a, uint32_t)
 {
+    uint32_t *block_sums = a.block_sums;
+    const int64_t nblocks = a.nblocks;
     __shared__ uint32_t s[SCAN_THREADS];
     uint32_t carry = 0;
     for (int64_t base = 0; base < nblocks; base += SCAN_THREADS) {
@@ -135,17 +181,31 @@ __global__ void k_scan_sums(uint32_t *block_sums, int64_t nblocks)
     }
     if (threadIdx.x == 0) block_sums[nblocks] = carry;
 }
-
-__global__ void k_scan_add(uint32_t *out, const uint32_t *block_sums, int64_t count,
-                           int64_t nblocks)
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(ScanSumsArgs a)
 {
-    int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_PER_THREAD;
-    uint32_t add = block_sums[blockIdx.x];
+    scan_sums_body(a, 0u);
+}
+SDPD_MULTI_KERNEL(k_scan_sums_multi, ScanSumsArgs, scan_sums_body, SCAN_THREADS)
+
+struct ScanAddArgs {
+    uint32_t *out;
+    const uint32_t *block_sums;
+    int64_t count, nblocks;
+};
+__device__ __forceinline__ void scan_add_body(const ScanAddArgs &a, uint32_t blk)
+{
+    int64_t base = (int64_t)blk * SCAN_BLOCK + threadIdx.x * SCAN_PER_THREAD;
+    uint32_t add = a.block_sums[blk];
 #pragma unroll
     for (int k = 0; k < SCAN_PER_THREAD; ++k)
-        if (base + k < count) out[base + k] += add;
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[count] = block_sums[nblocks];
+        if (base + k < a.count) a.out[base + k] += add;
+    if (blk == 0 && threadIdx.x == 0) a.out[a.count] = a.block_sums[a.nblocks];
 }
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_add(ScanAddArgs a)
+{
+    scan_add_body(a, blockIdx.x);
+}
+SDPD_MULTI_KERNEL(k_scan_add_multi, ScanAddArgs, scan_add_body, SCAN_THREADS)
 
 // out[0..count] = exclusive prefix sums of in[0..count), out[count] = total.
 // block_sums needs ceil(count / 1024) + 1 entries.  A value above cap sets
@@ -155,35 +215,52 @@ int run_scan(sdpd_ctx *c, const uint32_t *in, uint32_t *out, int64_t count, uint
 {
     const int64_t nb = (count + SCAN_BLOCK - 1) / SCAN_BLOCK;
     if (nb == 0) return launch_fill_u32(c, out, 0u, 1);
-    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, c->stream, in,
-                       count, cap, out, block_sums, c->err);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, c->stream, block_sums, nb);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, c->stream, out,
-                       block_sums, count, nb);
-    return check_hip(hipGetLastError());
+    int rc = launch_or_record(c, k_scan_local, k_scan_local_multi, (unsigned)nb, SCAN_THREADS, 0,
+                              ScanLocalArgs{in, count, cap, out, block_sums, c->err});
+    if (!rc)
+        rc = launch_or_record(c, k_scan_sums, k_scan_sums_multi, 1u, SCAN_THREADS, 0,
+                              ScanSumsArgs{block_sums, nb});
+    if (!rc)
+        rc = launch_or_record(c, k_scan_add, k_scan_add_multi, (unsigned)nb, SCAN_THREADS, 0,
+                              ScanAddArgs{out, block_sums, count, nb});
+    return rc;
 }
 
 // particle i goes to an arbitrary free position of its cell
-__global__ void k_scatter(const uint32_t *cell_of, const uint32_t *cell_start, uint32_t *cursor,
-                          uint32_t *tmp_idx, int64_t n)
+struct ScatterArgs {
+    const uint32_t *cell_of, *cell_start;
+    uint32_t *cursor, *tmp_idx;
+    int64_t n;
+};
+__device__ __forceinline__ void scatter_body(const ScatterArgs &a, uint32_t blk)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t c = cell_of[i];
-    uint32_t pos = cell_start[c] + wave_counted_inc(cursor, c);
-    tmp_idx[pos] = (uint32_t)i;
+    int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    uint32_t c = a.cell_of[i];
+    uint32_t pos = a.cell_start[c] + wave_counted_inc(a.cursor, c);
+    a.tmp_idx[pos] = (uint32_t)i;
 }
+__global__ void k_scatter(ScatterArgs a) { scatter_body(a, blockIdx.x); }
+SDPD_MULTI_KERNEL(k_scatter_multi, ScatterArgs, scatter_body, 256)
 
 // final position = cell start + rank of the id inside the cell (ties, which
 // only invalid input with repeated ids has, broken by the scatter position so
 // that every slot is written once); cells above the capacity keep the
 // scatter order (the overflow is reported by the scan)
-__global__ void k_rank(const uint32_t *tmp_idx, const uint32_t *cell_of,
-                       const uint32_t *cell_start, const uint32_t *id, uint32_t *perm, int64_t n,
-                       int cap)
+struct RankArgs {
+    const uint32_t *tmp_idx, *cell_of, *cell_start, *id;
+    uint32_t *perm;
+    int64_t n;
+    int cap;
+};
+__device__ __forceinline__ void rank_body(const RankArgs &a, uint32_t blk)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    const uint32_t *tmp_idx = a.tmp_idx, *cell_of = a.cell_of, *cell_start = a.cell_start,
+                   *id = a.id;
+    uint32_t *perm = a.perm;
+    const int cap = a.cap;
+    int64_t k = (int64_t)blk * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
     uint32_t i = tmp_idx[k];
     uint32_t c = cell_of[i];
     uint32_t s = cell_start[c], e = cell_start[c + 1];
@@ -198,16 +275,34 @@ __global__ void k_rank(const uint32_t *tmp_idx, const uint32_t *cell_of,
     }
     perm[s + rank] = i;
 }
+__global__ void k_rank(RankArgs a) { rank_body(a, blockIdx.x); }
+SDPD_MULTI_KERNEL(k_rank_multi, RankArgs, rank_body, 256)
 
 // gather into (cell, id) order; with qr (mixed precision) also the FP32
 // position relative to the particle's cell origin
-__global__ void k_gather(DevParams P, int64_t n, const uint32_t *perm, const uint32_t *cell_of,
-                         const double *q, const double *p, const double *eps, const double *rho,
-                         const double *f, const uint32_t *id, double *tq, double *tp,
-                         double *teps, double *trho, double *tf, uint32_t *tid,
-                         uint32_t *cell_sorted, float *qr, double *q4)
+struct GatherArgs {
+    DevParams P;
+    int64_t n;
+    const uint32_t *perm, *cell_of;
+    const double *q, *p, *eps, *rho, *f;
+    const uint32_t *id;
+    double *tq, *tp, *teps, *trho, *tf;
+    uint32_t *tid, *cell_sorted;
+    float *qr;
+    double *q4;
+};
+__device__ __forceinline__ void gather_body(const GatherArgs &a, uint32_t blk)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const DevParams &P = a.P;
+    const int64_t n = a.n;
+    const uint32_t *perm = a.perm, *cell_of = a.cell_of;
+    const double *q = a.q, *p = a.p, *eps = a.eps, *rho = a.rho, *f = a.f;
+    const uint32_t *id = a.id;
+    double *tq = a.tq, *tp = a.tp, *teps = a.teps, *trho = a.trho, *tf = a.tf;
+    uint32_t *tid = a.tid, *cell_sorted = a.cell_sorted;
+    float *qr = a.qr;
+    double *q4 = a.q4;
+    int64_t k = (int64_t)blk * blockDim.x + threadIdx.x;
     if (k >= n) return;
     uint32_t i = perm[k];
     if (qr) {
@@ -232,15 +327,26 @@ __global__ void k_gather(DevParams P, int64_t n, const uint32_t *perm, const uin
     tid[k] = id[i];
     cell_sorted[k] = cell_of[i];
 }
+__global__ void k_gather(GatherArgs a) { gather_body(a, blockIdx.x); }
+SDPD_MULTI_KERNEL(k_gather_multi, GatherArgs, gather_body, 256)
 
 // the sorted arrays back into the caller's state, one launch (f only when
 // it was gathered)
-__global__ void k_copy_back(int64_t n, const double *tq, const double *tp, const double *tf,
-                            const double *teps, const double *trho, const uint32_t *tid,
-                            double *q, double *p, double *f, double *eps, double *rho,
-                            uint32_t *id)
+struct CopyBackArgs {
+    int64_t n;
+    const double *tq, *tp, *tf, *teps, *trho;
+    const uint32_t *tid;
+    double *q, *p, *f, *eps, *rho;
+    uint32_t *id;
+};
+__device__ __forceinline__ void copy_back_body(const CopyBackArgs &a, uint32_t blk)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = a.n;
+    const double *tq = a.tq, *tp = a.tp, *tf = a.tf, *teps = a.teps, *trho = a.trho;
+    const uint32_t *tid = a.tid;
+    double *q = a.q, *p = a.p, *f = a.f, *eps = a.eps, *rho = a.rho;
+    uint32_t *id = a.id;
+    const int64_t k = (int64_t)blk * blockDim.x + threadIdx.x;
     if (k >= n) return;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -252,32 +358,38 @@ __global__ void k_copy_back(int64_t n, const double *tq, const double *tp, const
     rho[k] = trho[k];
     id[k] = tid[k];
 }
+__global__ void k_copy_back(CopyBackArgs a) { copy_back_body(a, blockIdx.x); }
+SDPD_MULTI_KERNEL(k_copy_back_multi, CopyBackArgs, copy_back_body, 256)
 
 static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-__global__ void k_incr_u64(unsigned long long *p)
+struct IncrArgs {
+    unsigned long long *p;
+};
+__device__ __forceinline__ void incr_u64_body(const IncrArgs &a, uint32_t)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p += 1ull;
+    if (threadIdx.x == 0) *a.p += 1ull;
 }
+__global__ void k_incr_u64(IncrArgs a) { incr_u64_body(a, 0u); }
+SDPD_MULTI_KERNEL(k_incr_u64_multi, IncrArgs, incr_u64_body, 64)
 
 int launch_incr_u64(sdpd_ctx *c, unsigned long long *p)
 {
-    hipLaunchKernelGGL(k_incr_u64, dim3(1), dim3(64), 0, c->stream, p);
-    return check_hip(hipGetLastError());
+    return launch_or_record(c, k_incr_u64, k_incr_u64_multi, 1u, 64, 0, IncrArgs{p});
 }
 
 int launch_fill_u32(sdpd_ctx *c, uint32_t *p, uint32_t v, int64_t n)
 {
     if (n <= 0) return SDPD_OK;
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, p, v, n);
-    return check_hip(hipGetLastError());
+    return launch_or_record(c, k_fill_u32, k_fill_u32_multi, blocks_for(n, 256), 256, 0,
+                            FillU32Args{p, v, n});
 }
 
 int launch_fill_u64(sdpd_ctx *c, unsigned long long *p, unsigned long long v, int64_t n)
 {
     if (n <= 0) return SDPD_OK;
-    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, p, v, n);
-    return check_hip(hipGetLastError());
+    return launch_or_record(c, k_fill_u64, k_fill_u64_multi, blocks_for(n, 256), 256, 0,
+                            FillU64Args{p, v, n});
 }
 
 // Sort the state by (cell, id).  With kick_drift the first half kick and the
@@ -289,27 +401,34 @@ int run_build_cells(sdpd_ctx *c, const sdpd_state *s, int kick_drift)
     timer_begin(c, TK_CELLS);
     if ((rc = launch_fill_u32(c, c->count, 0u, nc))) return rc;
     if ((rc = launch_fill_u32(c, c->cursor, 0u, nc))) return rc;
-    if (n > 0) {
-        hipLaunchKernelGGL(k_kick_drift_assign, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream,
-                           c->dp, s->q, s->p, s->f, kick_drift, c->cell_of, c->count, c->err);
-        if ((rc = check_hip(hipGetLastError()))) return rc;
-    }
+    if (n > 0 &&
+        (rc = launch_or_record(c, k_kick_drift_assign, k_kick_drift_assign_multi,
+                               blocks_for(n, 256), 256, 0,
+                               KickDriftArgs{c->dp, s->q, s->p, s->f, kick_drift, c->cell_of,
+                                             c->count, c->err})))
+        return rc;
     if ((rc = run_scan(c, c->count, c->cell_start, nc, c->block_sums, c->prm.cell_cap))) return rc;
     if (n > 0) {
         unsigned g = blocks_for(n, 256);
-        hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, c->stream, c->cell_of, c->cell_start,
-                           c->cursor, c->tmp_idx, n);
-        hipLaunchKernelGGL(k_rank, dim3(g), dim3(256), 0, c->stream, c->tmp_idx, c->cell_of,
-                           c->cell_start, s->id, c->perm, n, c->prm.cell_cap);
         // inside a step (kick_drift) the forces are recomputed before
         // anything reads them, so they are not carried through the sort
         double *tf = kick_drift ? nullptr : c->tf;
-        hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, c->dp, n, c->perm,
-                           c->cell_of, s->q, s->p, s->eps, s->rho, s->f, s->id, c->tq, c->tp,
-                           c->teps, c->trho, tf, c->tid, c->cell_sorted, c->qr, c->q4);
-        hipLaunchKernelGGL(k_copy_back, dim3(g), dim3(256), 0, c->stream, n, c->tq, c->tp, tf,
-                           c->teps, c->trho, c->tid, s->q, s->p, s->f, s->eps, s->rho, s->id);
-        if ((rc = check_hip(hipGetLastError()))) return rc;
+        rc = launch_or_record(c, k_scatter, k_scatter_multi, g, 256, 0,
+                              ScatterArgs{c->cell_of, c->cell_start, c->cursor, c->tmp_idx, n});
+        if (!rc)
+            rc = launch_or_record(c, k_rank, k_rank_multi, g, 256, 0,
+                                  RankArgs{c->tmp_idx, c->cell_of, c->cell_start, s->id, c->perm,
+                                           n, c->prm.cell_cap});
+        if (!rc)
+            rc = launch_or_record(c, k_gather, k_gather_multi, g, 256, 0,
+                                  GatherArgs{c->dp, n, c->perm, c->cell_of, s->q, s->p, s->eps,
+                                             s->rho, s->f, s->id, c->tq, c->tp, c->teps, c->trho,
+                                             tf, c->tid, c->cell_sorted, c->qr, c->q4});
+        if (!rc)
+            rc = launch_or_record(c, k_copy_back, k_copy_back_multi, g, 256, 0,
+                                  CopyBackArgs{n, c->tq, c->tp, tf, c->teps, c->trho, c->tid, s->q,
+                                               s->p, s->f, s->eps, s->rho, s->id});
+        if (rc) return rc;
     }
     timer_end(c, TK_CELLS);
     c->cells_valid = 1;

@@ -54,14 +54,29 @@ __device__ __forceinline__ uint64_t density_cell(const DevParams &P, const doubl
 // closer than h (L >= 4 h), in the same rounding as the plain form.  For all
 // 27 cells the bit of every active partner's slot is stored in
 // masks[k * n + i] (the own cell, k = 13, without i itself).
-__global__ __launch_bounds__(256) void k_density(DevParams P, const double *__restrict__ q4,
-                                                 const uint32_t *__restrict__ cell_sorted,
-                                                 const uint32_t *__restrict__ cell_start,
-                                                 double *rho, double *eps, int update_eps,
-                                                 uint64_t *__restrict__ masks,
-                                                 uint32_t *err, double *rho_w)
+struct DensityArgs {
+    DevParams P;
+    const double *q4;
+    const uint32_t *cell_sorted, *cell_start;
+    double *rho, *eps;
+    int update_eps;
+    uint64_t *masks;
+    uint32_t *err;
+    double *rho_w;
+};
+
+__device__ __forceinline__ void density_body(const DensityArgs &a, uint32_t blk)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const DevParams &P = a.P;
+    const double *__restrict__ q4 = a.q4;
+    const uint32_t *__restrict__ cell_sorted = a.cell_sorted;
+    const uint32_t *__restrict__ cell_start = a.cell_start;
+    double *rho = a.rho, *eps = a.eps;
+    const int update_eps = a.update_eps;
+    uint64_t *__restrict__ masks = a.masks;
+    uint32_t *err = a.err;
+    double *rho_w = a.rho_w;
+    const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
     const int64_t n = P.n;
     const uint32_t c = cell_sorted[i];
@@ -99,6 +114,8 @@ __global__ __launch_bounds__(256) void k_density(DevParams P, const double *__re
         eps[i] = e_new;
     }
 }
+__global__ __launch_bounds__(256) void k_density(DensityArgs a) { density_body(a, blockIdx.x); }
+SDPD_MULTI_KERNEL(k_density_multi, DensityArgs, density_body, 256)
 
 // The same pass with four lanes per particle, for boxes too small to fill
 // the GPU with a thread per particle (the pass is then bound by the length
@@ -146,14 +163,18 @@ __device__ __forceinline__ uint64_t density_cell_quad(const DevParams &P,
     return mask;
 }
 
-__global__ __launch_bounds__(256) void k_density_quad(DevParams P, const double *__restrict__ q4,
-                                                      const uint32_t *__restrict__ cell_sorted,
-                                                      const uint32_t *__restrict__ cell_start,
-                                                      double *rho, double *eps, int update_eps,
-                                                      uint64_t *__restrict__ masks,
-                                                      uint32_t *err, double *rho_w)
+__device__ __forceinline__ void density_quad_body(const DensityArgs &a, uint32_t blk)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const DevParams &P = a.P;
+    const double *__restrict__ q4 = a.q4;
+    const uint32_t *__restrict__ cell_sorted = a.cell_sorted;
+    const uint32_t *__restrict__ cell_start = a.cell_start;
+    double *rho = a.rho, *eps = a.eps;
+    const int update_eps = a.update_eps;
+    uint64_t *__restrict__ masks = a.masks;
+    uint32_t *err = a.err;
+    double *rho_w = a.rho_w;
+    const int64_t t = (int64_t)blk * blockDim.x + threadIdx.x;
     const int64_t n = P.n;
     const int64_t i = t >> 2;
     const int q = (int)(threadIdx.x & 3u), base = (int)(threadIdx.x & 63u) & ~3;
@@ -202,6 +223,11 @@ __global__ __launch_bounds__(256) void k_density_quad(DevParams P, const double 
         eps[i] = e_new;
     }
 }
+__global__ __launch_bounds__(256) void k_density_quad(DensityArgs a)
+{
+    density_quad_body(a, blockIdx.x);
+}
+SDPD_MULTI_KERNEL(k_density_quad_multi, DensityArgs, density_quad_body, 256)
 
 int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps, bool pack_rho)
 {
@@ -215,15 +241,16 @@ int run_density(sdpd_ctx *c, const sdpd_state *s, int update_eps, bool pack_rho)
         return rc;
     }
     timer_begin(c, TK_DENSITY);
-    if (c->n <= kQuadMaxParticles)
-        hipLaunchKernelGGL(k_density_quad, dim3((unsigned)((4 * c->n + 255) / 256)), dim3(256), 0,
-                           c->stream, c->dp, c->q4, c->cell_sorted, c->cell_start, s->rho,
-                           s->eps, update_eps, c->masks, c->err, pack_rho ? c->q4 : nullptr);
-    else
-        hipLaunchKernelGGL(k_density, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0,
-                           c->stream, c->dp, c->q4, c->cell_sorted, c->cell_start, s->rho,
-                           s->eps, update_eps, c->masks, c->err, pack_rho ? c->q4 : nullptr);
-    int rc = check_hip(hipGetLastError());
+    const DensityArgs args{c->dp, c->q4, c->cell_sorted, c->cell_start, s->rho, s->eps,
+                           update_eps, c->masks, c->err, pack_rho ? c->q4 : nullptr};
+    // four lanes per particle only where one lane per particle cannot fill
+    // the GPU: a small box on its own (not a box whose launches are recorded
+    // for a batch, where all boxes share each launch)
+    const int rc = c->n <= kQuadMaxParticles && !c->rec
+                       ? launch_or_record(c, k_density_quad, k_density_quad_multi,
+                                          (unsigned)((4 * c->n + 255) / 256), 256, 0, args)
+                       : launch_or_record(c, k_density, k_density_multi,
+                                          (unsigned)((c->n + 255) / 256), 256, 0, args);
     timer_end(c, TK_DENSITY);
     if (!rc) c->masks_valid = 1;
     return rc;

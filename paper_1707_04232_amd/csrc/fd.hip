@@ -464,18 +464,30 @@ __device__ __forceinline__ void fd_flush_counters(const FdCount &cnt, bool negep
     }
 }
 
-// one launch per group: workgroup b = blockIdx.x applies range b of L
+// one launch per group: workgroup b applies range b of L
+struct FdPhaseArgs {
+    const DevParams *Pp;
+    FdLaunch L;
+    FdArgs A;
+    unsigned long long *counters;
+};
 template <bool FAST>
-__global__ __launch_bounds__(64) void k_fd_phase(const DevParams *__restrict__ Pp, FdLaunch L,
-                                                 FdArgs A, unsigned long long *counters)
+__device__ __forceinline__ void fd_phase_body(const FdPhaseArgs &a, uint32_t blk)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     FdCount cnt = {0u, 0u, 0u, 0u, 0u};
     bool negeps = false;
     auto no_wait = [] {};
-    fd_range<FAST, false>(*Pp, L, (int64_t)blockIdx.x, lds, A, cnt, negeps, no_wait);
-    fd_flush_counters(cnt, negeps, counters, A.err);
+    fd_range<FAST, false>(*a.Pp, a.L, (int64_t)blk, lds, a.A, cnt, negeps, no_wait);
+    fd_flush_counters(cnt, negeps, a.counters, a.A.err);
 }
+template <bool FAST>
+__global__ __launch_bounds__(64) void k_fd_phase(FdPhaseArgs a)
+{
+    fd_phase_body<FAST>(a, blockIdx.x);
+}
+SDPD_MULTI_KERNEL(k_fd_phase_fast_multi, FdPhaseArgs, fd_phase_body<true>, 64)
+SDPD_MULTI_KERNEL(k_fd_phase_gen_multi, FdPhaseArgs, fd_phase_body<false>, 64)
 
 // The whole sweep in one launch.  Its ranges, group by group (group 0 =
 // phase 0, then the groups of mutually disjoint phases; inside a group in
@@ -671,6 +683,12 @@ void fd_default_tuning(sdpd_ctx *c)
                                 c->max_lds) != hipSuccess ||
             hipFuncSetAttribute((const void *)k_fd_sweep<true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                c->max_lds) != hipSuccess ||
+            hipFuncSetAttribute((const void *)k_fd_phase_fast_multi,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                c->max_lds) != hipSuccess ||
+            hipFuncSetAttribute((const void *)k_fd_phase_gen_multi,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                 c->max_lds) != hipSuccess) {
             (void)hipGetLastError();
             c->max_lds = 65536;
@@ -793,11 +811,13 @@ static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, in
     const size_t lds = fd_lds_bytes(L.cap_p, L.cap_e);
     if (lds > (size_t)c->max_lds) return SDPD_EINVAL;
     timer_begin(c, TK_FD);
-    auto kern = fd_fast(c) ? k_fd_phase<true> : k_fd_phase<false>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)wg), dim3(64), lds, c->stream, c->dparams, L,
-                       fd_args(c, s, dt_fd), c->counters);
+    const FdPhaseArgs args{c->dparams, L, fd_args(c, s, dt_fd), c->counters};
+    const int rc = fd_fast(c) ? launch_or_record(c, k_fd_phase<true>, k_fd_phase_fast_multi,
+                                                 (unsigned)wg, 64, lds, args)
+                              : launch_or_record(c, k_fd_phase<false>, k_fd_phase_gen_multi,
+                                                 (unsigned)wg, 64, lds, args);
     timer_end(c, TK_FD);
-    return check_hip(hipGetLastError());
+    return rc;
 }
 
 // cells of task T (the host form of task_cells); B = -1 for a phase-0 task
@@ -935,10 +955,18 @@ int fd_prepare_sweep(sdpd_ctx *c)
 }
 
 // (x, y, z, rho) record of every particle for the pair gathers of the sweep
-__global__ void k_pack_qrho(int64_t n, const double *__restrict__ q,
-                            const double *__restrict__ rho, double4 *qrho)
+struct PackArgs {
+    int64_t n;
+    const double *q, *rho;
+    double4 *qrho;
+};
+__device__ __forceinline__ void pack_qrho_body(const PackArgs &a, uint32_t blk)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = a.n;
+    const double *__restrict__ q = a.q;
+    const double *__restrict__ rho = a.rho;
+    double4 *qrho = a.qrho;
+    const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double4 r;
     r.x = q[i];
@@ -947,6 +975,8 @@ __global__ void k_pack_qrho(int64_t n, const double *__restrict__ q,
     r.w = rho[i];
     qrho[i] = r;
 }
+__global__ void k_pack_qrho(PackArgs a) { pack_qrho_body(a, blockIdx.x); }
+SDPD_MULTI_KERNEL(k_pack_qrho_multi, PackArgs, pack_qrho_body, 256)
 
 // Schedule and packed records of a sweep (independent of the tuning), then
 // its launches.
@@ -956,10 +986,11 @@ int fd_sweep_prepare(sdpd_ctx *c, const sdpd_state *s, bool packed)
     if (rc) return rc;
     if (!packed) {
         timer_begin(c, TK_SCHED);   // sweep preparation, with the schedule
-        hipLaunchKernelGGL(k_pack_qrho, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0,
-                           c->stream, c->n, s->q, s->rho, reinterpret_cast<double4 *>(c->q4));
+        rc = launch_or_record(c, k_pack_qrho, k_pack_qrho_multi, (unsigned)((c->n + 255) / 256),
+                              256, 0,
+                              PackArgs{c->n, s->q, s->rho, reinterpret_cast<double4 *>(c->q4)});
         timer_end(c, TK_SCHED);
-        if ((rc = check_hip(hipGetLastError()))) return rc;
+        if (rc) return rc;
     }
     c->fd_swept = 1;
     return SDPD_OK;

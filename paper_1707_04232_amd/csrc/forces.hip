@@ -23,10 +23,17 @@ __device__ __forceinline__ double kernel_f(const DevParams &P, double r)
 // P_i / rho_i^2 from the ideal-gas closure: A kB rho eps / (m Cv) / rho^2
 // Pi_i = P_i / rho_i^2, stored with the position as (x, y, z, Pi) so that
 // the force pass reads one 32-byte record per partner
-__global__ void k_pressure_term(DevParams P, const double *q, const double *eps,
-                                const double *rho, double *q4)
+struct PressureArgs {
+    DevParams P;
+    const double *q, *eps, *rho;
+    double *q4;
+};
+__device__ __forceinline__ void pressure_term_body(const PressureArgs &a, uint32_t blk)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const DevParams &P = a.P;
+    const double *q = a.q, *eps = a.eps, *rho = a.rho;
+    double *q4 = a.q4;
+    int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
     const double v = P.cPi * eps[i] / rho[i];
     double4 r;
@@ -36,18 +43,31 @@ __global__ void k_pressure_term(DevParams P, const double *q, const double *eps,
     r.w = v;
     reinterpret_cast<double4 *>(q4)[i] = r;
 }
+__global__ void k_pressure_term(PressureArgs a) { pressure_term_body(a, blockIdx.x); }
+SDPD_MULTI_KERNEL(k_pressure_term_multi, PressureArgs, pressure_term_body, 256)
 
 // f_i = sum_{j != i, r < h} m^2 (Pi_i + Pi_j) F_ij r_ij over the partners
 // recorded in the 27 active-pair masks of the density pass (same positions),
 // in the fixed order (offset index, then slot); optionally p_i += dt/2 f_i.
 // Only the set bits of each mask are visited.
-__global__ __launch_bounds__(256) void k_forces(DevParams P, const double *__restrict__ q4,
-                                                const uint32_t *__restrict__ cell_sorted,
-                                                const uint32_t *__restrict__ cell_start,
-                                                const uint64_t *__restrict__ masks,
-                                                double *f, double *p, int half_kick)
+struct ForcesArgs {
+    DevParams P;
+    const double *q4;
+    const uint32_t *cell_sorted, *cell_start;
+    const uint64_t *masks;
+    double *f, *p;
+    int half_kick;
+};
+__device__ __forceinline__ void forces_body(const ForcesArgs &a, uint32_t blk)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const DevParams &P = a.P;
+    const double *__restrict__ q4 = a.q4;
+    const uint32_t *__restrict__ cell_sorted = a.cell_sorted;
+    const uint32_t *__restrict__ cell_start = a.cell_start;
+    const uint64_t *__restrict__ masks = a.masks;
+    double *f = a.f, *p = a.p;
+    const int half_kick = a.half_kick;
+    const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
     const int64_t n = P.n;
     const uint32_t c = cell_sorted[i];
@@ -92,6 +112,8 @@ __global__ __launch_bounds__(256) void k_forces(DevParams P, const double *__res
         p[2 * n + i] += hd * fz;
     }
 }
+__global__ __launch_bounds__(256) void k_forces(ForcesArgs a) { forces_body(a, blockIdx.x); }
+SDPD_MULTI_KERNEL(k_forces_multi, ForcesArgs, forces_body, 256)
 
 int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick)
 {
@@ -99,11 +121,12 @@ int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick)
     if (c->dp.mixed) return run_forces_f32(c, s, half_kick);
     const unsigned g = (unsigned)((c->n + 255) / 256);
     timer_begin(c, TK_FORCE);
-    hipLaunchKernelGGL(k_pressure_term, dim3(g), dim3(256), 0, c->stream, c->dp, s->q, s->eps,
-                       s->rho, c->q4);
-    hipLaunchKernelGGL(k_forces, dim3(g), dim3(256), 0, c->stream, c->dp, c->q4,
-                       c->cell_sorted, c->cell_start, c->masks, s->f, s->p, half_kick);
-    int rc = check_hip(hipGetLastError());
+    int rc = launch_or_record(c, k_pressure_term, k_pressure_term_multi, g, 256, 0,
+                              PressureArgs{c->dp, s->q, s->eps, s->rho, c->q4});
+    if (!rc)
+        rc = launch_or_record(c, k_forces, k_forces_multi, g, 256, 0,
+                              ForcesArgs{c->dp, c->q4, c->cell_sorted, c->cell_start, c->masks,
+                                         s->f, s->p, half_kick});
     timer_end(c, TK_FORCE);
     return rc;
 }

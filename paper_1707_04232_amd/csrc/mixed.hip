@@ -49,14 +49,26 @@ __device__ __forceinline__ NbCellF neighbour_cell_f32(const DevParams &P, int cx
 
 // One thread per particle; candidates of the 27 cells in the fixed order;
 // masks[k * n + i] as in the FP64 pass (bit = slot of an active partner).
-__global__ __launch_bounds__(256) void k_density_f32(DevParams P, const float *__restrict__ qr,
-                                                     const uint32_t *__restrict__ cell_sorted,
-                                                     const uint32_t *__restrict__ cell_start,
-                                                     double *rho, double *eps, int update_eps,
-                                                     uint64_t *__restrict__ masks,
-                                                     uint32_t *err)
+struct DensityF32Args {
+    DevParams P;
+    const float *qr;
+    const uint32_t *cell_sorted, *cell_start;
+    double *rho, *eps;
+    int update_eps;
+    uint64_t *masks;
+    uint32_t *err;
+};
+__device__ __forceinline__ void density_f32_body(const DensityF32Args &a, uint32_t blk)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const DevParams &P = a.P;
+    const float *__restrict__ qr = a.qr;
+    const uint32_t *__restrict__ cell_sorted = a.cell_sorted;
+    const uint32_t *__restrict__ cell_start = a.cell_start;
+    double *rho = a.rho, *eps = a.eps;
+    const int update_eps = a.update_eps;
+    uint64_t *__restrict__ masks = a.masks;
+    uint32_t *err = a.err;
+    const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
     const int64_t n = P.n;
     const uint32_t c = cell_sorted[i];
@@ -95,23 +107,45 @@ __global__ __launch_bounds__(256) void k_density_f32(DevParams P, const float *_
         eps[i] = e_new;
     }
 }
-
-__global__ void k_pressure_term_f32(DevParams P, const double *eps, const double *rho,
-                                    float *pi_f)
+__global__ __launch_bounds__(256) void k_density_f32(DensityF32Args a)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < P.n) pi_f[i] = (float)(P.cPi * eps[i] / rho[i]);
+    density_f32_body(a, blockIdx.x);
 }
+SDPD_MULTI_KERNEL(k_density_f32_multi, DensityF32Args, density_f32_body, 256)
+
+struct PressureF32Args {
+    DevParams P;
+    const double *eps, *rho;
+    float *pi_f;
+};
+__device__ __forceinline__ void pressure_term_f32_body(const PressureF32Args &a, uint32_t blk)
+{
+    int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
+    if (i < a.P.n) a.pi_f[i] = (float)(a.P.cPi * a.eps[i] / a.rho[i]);
+}
+__global__ void k_pressure_term_f32(PressureF32Args a) { pressure_term_f32_body(a, blockIdx.x); }
+SDPD_MULTI_KERNEL(k_pressure_term_f32_multi, PressureF32Args, pressure_term_f32_body, 256)
 
 // f_i over the partners recorded by the density pass, FP32 terms and sums
-__global__ __launch_bounds__(256) void k_forces_f32(DevParams P, const float *__restrict__ qr,
-                                                    const float *__restrict__ pi_f,
-                                                    const uint32_t *__restrict__ cell_sorted,
-                                                    const uint32_t *__restrict__ cell_start,
-                                                    const uint64_t *__restrict__ masks,
-                                                    double *f, double *p, int half_kick)
+struct ForcesF32Args {
+    DevParams P;
+    const float *qr, *pi_f;
+    const uint32_t *cell_sorted, *cell_start;
+    const uint64_t *masks;
+    double *f, *p;
+    int half_kick;
+};
+__device__ __forceinline__ void forces_f32_body(const ForcesF32Args &a, uint32_t blk)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const DevParams &P = a.P;
+    const float *__restrict__ qr = a.qr;
+    const float *__restrict__ pi_f = a.pi_f;
+    const uint32_t *__restrict__ cell_sorted = a.cell_sorted;
+    const uint32_t *__restrict__ cell_start = a.cell_start;
+    const uint64_t *__restrict__ masks = a.masks;
+    double *f = a.f, *p = a.p;
+    const int half_kick = a.half_kick;
+    const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
     const int64_t n = P.n;
     const uint32_t c = cell_sorted[i];
@@ -151,14 +185,19 @@ __global__ __launch_bounds__(256) void k_forces_f32(DevParams P, const float *__
         p[2 * n + i] += hd * gz;
     }
 }
+__global__ __launch_bounds__(256) void k_forces_f32(ForcesF32Args a)
+{
+    forces_f32_body(a, blockIdx.x);
+}
+SDPD_MULTI_KERNEL(k_forces_f32_multi, ForcesF32Args, forces_f32_body, 256)
 
 int run_density_f32(sdpd_ctx *c, const sdpd_state *s, int update_eps)
 {
     timer_begin(c, TK_DENSITY);
-    hipLaunchKernelGGL(k_density_f32, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0,
-                       c->stream, c->dp, c->qr, c->cell_sorted, c->cell_start, s->rho, s->eps,
-                       update_eps, c->masks, c->err);
-    int rc = check_hip(hipGetLastError());
+    const int rc = launch_or_record(c, k_density_f32, k_density_f32_multi,
+                                    (unsigned)((c->n + 255) / 256), 256, 0,
+                                    DensityF32Args{c->dp, c->qr, c->cell_sorted, c->cell_start,
+                                                   s->rho, s->eps, update_eps, c->masks, c->err});
     timer_end(c, TK_DENSITY);
     return rc;
 }
@@ -167,11 +206,12 @@ int run_forces_f32(sdpd_ctx *c, const sdpd_state *s, int half_kick)
 {
     const unsigned g = (unsigned)((c->n + 255) / 256);
     timer_begin(c, TK_FORCE);
-    hipLaunchKernelGGL(k_pressure_term_f32, dim3(g), dim3(256), 0, c->stream, c->dp, s->eps,
-                       s->rho, c->pi_f);
-    hipLaunchKernelGGL(k_forces_f32, dim3(g), dim3(256), 0, c->stream, c->dp, c->qr, c->pi_f,
-                       c->cell_sorted, c->cell_start, c->masks, s->f, s->p, half_kick);
-    int rc = check_hip(hipGetLastError());
+    int rc = launch_or_record(c, k_pressure_term_f32, k_pressure_term_f32_multi, g, 256, 0,
+                              PressureF32Args{c->dp, s->eps, s->rho, c->pi_f});
+    if (!rc)
+        rc = launch_or_record(c, k_forces_f32, k_forces_f32_multi, g, 256, 0,
+                              ForcesF32Args{c->dp, c->qr, c->pi_f, c->cell_sorted, c->cell_start,
+                                            c->masks, s->f, s->p, half_kick});
     timer_end(c, TK_FORCE);
     return rc;
 }

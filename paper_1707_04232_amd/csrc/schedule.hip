@@ -28,13 +28,20 @@ namespace sdpd {
 constexpr int COUNT_WAVES = 4;     // waves per workgroup
 constexpr int COUNT_LANES = 16;    // lanes per task: four tasks per wave
 
-__global__ __launch_bounds__(64 * COUNT_WAVES) void k_task_count(
-    const DevParams *__restrict__ Pp, const uint32_t *__restrict__ cell_start,
-    const uint64_t *__restrict__ masks, uint32_t *tcount, uint32_t *tnp)
+struct TaskCountArgs {
+    const DevParams *Pp;
+    const uint32_t *cell_start;
+    const uint64_t *masks;
+    uint32_t *tcount, *tnp;
+};
+__device__ __forceinline__ void task_count_body(const TaskCountArgs &a, uint32_t blk)
 {
-    const DevParams &P = *Pp;
+    const DevParams &P = *a.Pp;
+    const uint32_t *__restrict__ cell_start = a.cell_start;
+    const uint64_t *__restrict__ masks = a.masks;
+    uint32_t *tcount = a.tcount, *tnp = a.tnp;
     const int lane = threadIdx.x & 63, x = lane & (COUNT_LANES - 1);
-    const int64_t T = ((int64_t)blockIdx.x * COUNT_WAVES + (threadIdx.x >> 6)) * (64 / COUNT_LANES) +
+    const int64_t T = ((int64_t)blk * COUNT_WAVES + (threadIdx.x >> 6)) * (64 / COUNT_LANES) +
                       lane / COUNT_LANES;
     const bool ok = T < (int64_t)NMASK * P.ncell;
     uint32_t c = 0, na = 0;
@@ -66,6 +73,11 @@ __global__ __launch_bounds__(64 * COUNT_WAVES) void k_task_count(
         tnp[T] = na + (slot == 0 ? 0u : (uint32_t)__popcll(orb));
     }
 }
+__global__ __launch_bounds__(64 * COUNT_WAVES) void k_task_count(TaskCountArgs a)
+{
+    task_count_body(a, blockIdx.x);
+}
+SDPD_MULTI_KERNEL(k_task_count_multi, TaskCountArgs, task_count_body, 64 * COUNT_WAVES)
 
 struct TaskSpan {
     TaskCells tc;
@@ -187,23 +199,35 @@ __device__ __forceinline__ void schedule_segment(const DevParams &P, const TaskS
 // particles, otherwise one after the other on the whole wave.
 constexpr int SCHED_WAVES = 4;   // waves per workgroup, each on its own task pairs
 
-__global__ __launch_bounds__(64 * SCHED_WAVES) void k_schedule(const DevParams *__restrict__ Pp,
-                                                 const uint32_t *__restrict__ cell_start,
-                                                 const uint64_t *__restrict__ masks,
-                                                 const uint32_t *__restrict__ pair_off,
-                                                 const uint32_t *__restrict__ part_off,
-                                                 uint64_t *pairs, uint32_t *part_list,
-                                                 uint32_t pair_cap, uint32_t part_cap,
-                                                 uint32_t *err)
+struct ScheduleArgs {
+    const DevParams *Pp;
+    const uint32_t *cell_start;
+    const uint64_t *masks;
+    const uint32_t *pair_off, *part_off;
+    uint64_t *pairs;
+    uint32_t *part_list;
+    uint32_t pair_cap, part_cap;
+    uint32_t *err;
+    uint32_t nblk;   // workgroups of the box's grid-stride loop
+};
+__device__ __forceinline__ void schedule_body(const ScheduleArgs &a, uint32_t blk)
 {
-    const DevParams &P = *Pp;
+    const DevParams &P = *a.Pp;
+    const uint32_t *__restrict__ cell_start = a.cell_start;
+    const uint64_t *__restrict__ masks = a.masks;
+    const uint32_t *__restrict__ pair_off = a.pair_off;
+    const uint32_t *__restrict__ part_off = a.part_off;
+    uint64_t *pairs = a.pairs;
+    uint32_t *part_list = a.part_list;
+    const uint32_t pair_cap = a.pair_cap, part_cap = a.part_cap;
+    uint32_t *err = a.err;
     const int64_t ntask = (int64_t)NMASK * P.ncell;
     // wave index made explicitly uniform: the task arithmetic below then runs
     // on the scalar unit once per wave
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    for (int64_t Wp = (int64_t)blockIdx.x * SCHED_WAVES + wave; 2 * Wp < ntask;
-         Wp += (int64_t)gridDim.x * SCHED_WAVES) {
+    for (int64_t Wp = (int64_t)blk * SCHED_WAVES + wave; 2 * Wp < ntask;
+         Wp += (int64_t)a.nblk * SCHED_WAVES) {
         const TaskSpan ta = task_span(P, cell_start, pair_off, part_off, 2 * Wp);
         const TaskSpan tb = task_span(P, cell_start, pair_off, part_off, 2 * Wp + 1);
         bool oka = ta.e1 > ta.e0, okb = tb.e1 > tb.e0;
@@ -240,26 +264,32 @@ __global__ __launch_bounds__(64 * SCHED_WAVES) void k_schedule(const DevParams *
     }
 }
 
+__global__ __launch_bounds__(64 * SCHED_WAVES) void k_schedule(ScheduleArgs a)
+{
+    schedule_body(a, blockIdx.x);
+}
+SDPD_MULTI_KERNEL(k_schedule_multi, ScheduleArgs, schedule_body, 64 * SCHED_WAVES)
+
 int run_schedule(sdpd_ctx *c)
 {
     const int64_t ntask = (int64_t)NMASK * c->ncell;
     timer_begin(c, TK_SCHED);
     const int64_t per_block = (int64_t)COUNT_WAVES * (64 / COUNT_LANES);
     const int64_t count_blocks = (ntask + per_block - 1) / per_block;
-    hipLaunchKernelGGL(k_task_count, dim3((unsigned)count_blocks), dim3(64 * COUNT_WAVES), 0,
-                       c->stream, c->dparams, c->cell_start, c->masks, c->task_count, c->task_np);
-    int rc = check_hip(hipGetLastError());
+    int rc = launch_or_record(c, k_task_count, k_task_count_multi, (unsigned)count_blocks,
+                              64 * COUNT_WAVES, 0,
+                              TaskCountArgs{c->dparams, c->cell_start, c->masks, c->task_count,
+                                            c->task_np});
     if (rc) return rc;
     if ((rc = run_scan(c, c->task_count, c->pair_off, ntask, c->block_sums, -1))) return rc;
     if ((rc = run_scan(c, c->task_np, c->part_off, ntask, c->block_sums, -1))) return rc;
     // one workgroup per pair of tasks: many independent short waves hide the
     // load latency
     const int64_t grid = std::min<int64_t>((ntask / 2 + SCHED_WAVES - 1) / SCHED_WAVES, 0x7fffffffLL);
-    hipLaunchKernelGGL(k_schedule, dim3((unsigned)grid), dim3(64 * SCHED_WAVES), 0, c->stream,
-                       c->dparams,
-                       c->cell_start, c->masks, c->pair_off, c->part_off, c->pairs, c->part_list,
-                       (uint32_t)c->pair_cap, (uint32_t)c->part_cap, c->err);
-    rc = check_hip(hipGetLastError());
+    rc = launch_or_record(c, k_schedule, k_schedule_multi, (unsigned)grid, 64 * SCHED_WAVES, 0,
+                          ScheduleArgs{c->dparams, c->cell_start, c->masks, c->pair_off,
+                                       c->part_off, c->pairs, c->part_list, (uint32_t)c->pair_cap,
+                                       (uint32_t)c->part_cap, c->err, (uint32_t)grid});
     timer_end(c, TK_SCHED);
     return rc;
 }

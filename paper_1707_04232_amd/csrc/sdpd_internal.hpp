@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string.h>
+
 #include <vector>
 
 #include "sdpd.h"
@@ -75,6 +77,37 @@ struct Timer {
     size_t used = 0;
 };
 
+// ---------------------------------------------------------------- multi-box launches
+// Every kernel of a step has an argument struct A, a body
+// `body(const A &a, uint32_t blk)` (blk in place of blockIdx.x), a
+// single-box kernel `k(A a)` and a multi-box kernel that runs, in one launch,
+// workgroup blk of box w.x for every (w.x, w.y = blk) of a table: the boxes'
+// argument structs are an array in device memory.  A context in recording
+// mode appends its launches to a LaunchRecord instead of issuing them; the
+// batch of many boxes (batch.hip) merges the boxes' records into multi-box
+// launches, one per kernel and position of the step.
+using MultiKernel = void (*)(const void *, const uint2 *);
+
+struct RecordedLaunch {
+    MultiKernel multi;
+    unsigned grid, block;
+    size_t lds;
+    std::vector<unsigned char> args;
+};
+using LaunchRecord = std::vector<RecordedLaunch>;
+
+// (the table is read-only for the whole launch: restrict lets the compiler
+// keep argument fields across the body's stores, as it does for kernel
+// arguments)
+#define SDPD_MULTI_KERNEL(NAME, ARGS, BODY, THREADS)                                          \
+    __global__ __launch_bounds__(THREADS) void NAME(const void *__restrict__ tab,              \
+                                                    const uint2 *__restrict__ wg)              \
+    {                                                                                          \
+        const uint2 w = wg[blockIdx.x];                                                        \
+        const ARGS *__restrict__ t = static_cast<const ARGS *>(tab);                           \
+        BODY(t[w.x], w.y);                                                                     \
+    }
+
 }  // namespace sdpd
 
 struct sdpd_ctx {
@@ -120,6 +153,7 @@ struct sdpd_ctx {
     sdpd::AdjointWork *adj;      // checkpoints and cotangents of the adjoint (lazily)
     int64_t pair_cap, part_cap;
     sdpd::Timer timer;
+    sdpd::LaunchRecord *rec = nullptr;   // recording mode: launches are appended here
     int timing;
     double last_fd_ms;
     int64_t last_fd_launches;
@@ -170,6 +204,28 @@ void adjoint_free(AdjointWork *a);
 // event timing around one launch of class k (no-op unless c->timing)
 void timer_begin(sdpd_ctx *c, int k);
 void timer_end(sdpd_ctx *c, int k);
+
+// Issue kernel `single` with `args` on the context's stream, or (recording
+// mode) append the launch with its multi-box form.  grid 0 launches nothing.
+template <class A>
+int launch_or_record(sdpd_ctx *c, void (*single)(A), MultiKernel multi, unsigned grid,
+                     unsigned block, size_t lds, const A &args)
+{
+    if (grid == 0) return SDPD_OK;
+    if (c->rec) {
+        RecordedLaunch r;
+        r.multi = multi;
+        r.grid = grid;
+        r.block = block;
+        r.lds = lds;
+        r.args.resize(sizeof(A));
+        memcpy(r.args.data(), &args, sizeof(A));
+        c->rec->push_back(std::move(r));
+        return SDPD_OK;
+    }
+    hipLaunchKernelGGL(single, dim3(grid), dim3(block), lds, c->stream, args);
+    return check_hip(hipGetLastError());
+}
 
 }  // namespace sdpd
 

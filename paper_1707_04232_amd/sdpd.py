@@ -18,6 +18,7 @@ KERNEL_LUCY, KERNEL_CUBIC = 0, 1
 FD_EMS, FD_AMS, FD_SSA, FD_NONE = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 SWEEP_AUTO, SWEEP_ONE, SWEEP_PER_GROUP = 0, 1, 2
+BATCH_AUTO, BATCH_FUSED, BATCH_GRAPHS = 0, 1, 2
 TIMING_CLASSES = ("cells", "density", "fd", "forces", "observe", "schedule")
 
 EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
@@ -26,8 +27,8 @@ EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
            "sdpd_set_timing", "sdpd_timing", "sdpd_tune", "sdpd_get_tuning",
            "sdpd_fd_schedule_size", "sdpd_set_sweep_mode", "sdpd_sweep_mode", "sdpd_autotune",
            "sdpd_set_timing_mask",
-           "sdpd_batch_create", "sdpd_batch_run",
-           "sdpd_batch_destroy", "sdpd_adjoint_forward", "sdpd_adjoint_backward",
+           "sdpd_batch_create", "sdpd_batch_create_layout", "sdpd_batch_layout",
+           "sdpd_batch_run", "sdpd_batch_destroy", "sdpd_adjoint_forward", "sdpd_adjoint_backward",
            "sdpd_adjoint_vjp", "sdpd_observe_noalloc", "sdpd_strerror",
            "sdpd_abi_version")
 
@@ -112,6 +113,9 @@ def lib():
             "sdpd_get_tuning": [vp, C.POINTER(_Tuning)],
             "sdpd_fd_schedule_size": [vp, C.POINTER(i64), C.POINTER(i64)],
             "sdpd_batch_create": [C.POINTER(vp), C.POINTER(_State), i32, C.POINTER(vp)],
+            "sdpd_batch_create_layout": [C.POINTER(vp), C.POINTER(_State), i32, i32, i32,
+                                         C.POINTER(vp)],
+            "sdpd_batch_layout": [vp],
             "sdpd_batch_run": [vp, u64, i32],
             "sdpd_batch_destroy": [vp],
             "sdpd_adjoint_forward": [vp, SP, i32, i32],
@@ -402,17 +406,26 @@ class Context:
 
 
 class Batch:
-    """Many boxes (contexts with their states) advanced by one HIP graph."""
+    """Many boxes (contexts with their states) advanced together: by default
+    every stage of a step is one launch for all boxes (BATCH_FUSED); with
+    BATCH_GRAPHS each box's own launches are captured."""
 
-    def __init__(self, contexts, states):
+    def __init__(self, contexts, states, layout=BATCH_AUTO, parts=0):
         self._ctx = list(contexts)
         self._st = list(states)
         n = len(self._ctx)
         handles = (C.c_void_p * n)(*[c._h.value for c in self._ctx])
         self._cst = (_State * n)(*[s.c() for s in self._st])
         self._h = C.c_void_p()
-        _check(lib().sdpd_batch_create(handles, self._cst, n, C.byref(self._h)),
-               "sdpd_batch_create")
+        _check(lib().sdpd_batch_create_layout(handles, self._cst, n, int(layout), int(parts),
+                                              C.byref(self._h)), "sdpd_batch_create_layout")
+
+    def layout(self) -> int:
+        """The layout in use (BATCH_FUSED or BATCH_GRAPHS)."""
+        m = lib().sdpd_batch_layout(self._h)
+        if m < 0:
+            _check(m, "sdpd_batch_layout")
+        return m
 
     def run(self, step0: int, nsteps: int):
         _check(lib().sdpd_batch_run(self._h, int(step0), int(nsteps)), "sdpd_batch_run")

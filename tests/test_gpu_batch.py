@@ -39,16 +39,19 @@ def _boxes(nbox, fd_every, streams):
     return out
 
 
+@pytest.mark.parametrize("layout", ["fused", "graphs"])
 @pytest.mark.parametrize("fd_every", [1, 2])
-def test_batch_graph_matches_eager_steps(fd_every):
+def test_batch_graph_matches_eager_steps(fd_every, layout):
     import torch
     from paper_1707_04232_amd import sdpd
-    say("batch graph vs eager, fd_every", fd_every)
+    say("batch vs eager, fd_every", fd_every, "layout", layout)
     streams = [torch.cuda.Stream() for _ in range(3)]
     ref = _boxes(6, fd_every, None)
     bat = _boxes(6, fd_every, streams)
     torch.cuda.synchronize()
-    with sdpd.Batch([c for c, _ in bat], [s for _, s in bat]) as B:
+    want = sdpd.BATCH_FUSED if layout == "fused" else sdpd.BATCH_GRAPHS
+    with sdpd.Batch([c for c, _ in bat], [s for _, s in bat], layout=want) as B:
+        assert B.layout() == want
         with pytest.raises(sdpd.SdpdError):
             if fd_every > 1:
                 B.run(1, fd_every)         # blocks must start at a multiple of fd_every
@@ -85,7 +88,7 @@ streams = [torch.cuda.Stream() for _ in range(3)]
 ref = _boxes(6, 1, None)
 bat = _boxes(6, 1, streams)
 torch.cuda.synchronize()
-with sdpd.Batch([c for c, _ in bat], [s for _, s in bat]) as B:
+with sdpd.Batch([c for c, _ in bat], [s for _, s in bat], layout=sdpd.BATCH_GRAPHS) as B:
     step = 0
     for rep in range(3):
         B.run(step, 2)
@@ -120,14 +123,16 @@ def test_batch_per_stream_graphs_match_eager_steps():
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout[-2000:] + r.stderr[-2000:]
 
 
-def test_batch_refuses_a_retuned_context():
+@pytest.mark.parametrize("layout", ["fused", "graphs"])
+def test_batch_refuses_a_retuned_context(layout):
     import torch
     from paper_1707_04232_amd import sdpd
-    say("batch after sdpd_tune")
+    say("batch after sdpd_tune", layout)
     streams = [torch.cuda.Stream() for _ in range(2)]
     bat = _boxes(2, 1, streams)
     torch.cuda.synchronize()
-    with sdpd.Batch([c for c, _ in bat], [s for _, s in bat]) as B:
+    want = sdpd.BATCH_FUSED if layout == "fused" else sdpd.BATCH_GRAPHS
+    with sdpd.Batch([c for c, _ in bat], [s for _, s in bat], layout=want) as B:
         B.run(0, 1)
         t = bat[0][0].get_tuning()
         bat[0][0].tune(t["fd_tasks"], t["lds_particles"], t["lds_pairs"])
@@ -233,4 +238,51 @@ def test_batch_boxes_match_oracle():
                     if resync:
                         PU.load_state(S, Rs[b])
     for c, _ in bat:
+        c.close()
+
+
+def test_fused_batch_mixed_precision_and_schemes_match_eager():
+    """Boxes of different precision (FP64 and the FP32 density/force form),
+    schemes (EMS, AMS), kernels and sizes (one above the four-lane density
+    limit of 2^17 particles) in one fused batch: every box bit-identical to
+    its eager steps."""
+    import torch
+    from paper_1707_04232_amd import sdpd
+    say("fused batch: mixed precisions and schemes")
+    specs = [dict(side=10, prec=sdpd.MIXED), dict(side=12, fd=sdpd.FD_AMS),
+             dict(side=11, kernel=sdpd.KERNEL_CUBIC, zeta=0.3),
+             dict(side=52, prec=sdpd.FP64), dict(side=13, prec=sdpd.MIXED, fd=sdpd.FD_AMS)]
+
+    def make(streams):
+        out = []
+        for b, sp in enumerate(specs):
+            sp = dict(sp)
+            side = sp.pop("side")
+            q, p, eps, ids = lattice_state(side, Cv=3.0, T=0.5, seed=20 + b)
+            prm = sdpd.SdpdParams(n=len(eps), box=float(side), Cv=3.0, replica=b, seed=11, **sp)
+            S = sdpd.DeviceState.from_numpy(q, p, eps, ids)
+            st = streams[b % len(streams)] if streams else torch.cuda.current_stream()
+            with torch.cuda.stream(st):
+                ctx = sdpd.Context(prm)
+            ctx.prepare(S)
+            out.append((ctx, S))
+        return out
+
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    ref = make(None)
+    bat = make(streams)
+    torch.cuda.synchronize()
+    with sdpd.Batch([c for c, _ in bat], [s for _, s in bat]) as B:
+        assert B.layout() == sdpd.BATCH_FUSED
+        for rep in range(2):
+            B.run(3 * rep, 3)
+            for c, S in ref:
+                c.step(S, 3 * rep, 3, stats=False)
+            for (cb, Sb), (cr, Sr) in zip(bat, ref):
+                cb.sync()
+                cr.sync()
+                gb, gr = Sb.to_numpy(), Sr.to_numpy()
+                for k in ("q", "p", "eps", "rho", "f", "id"):
+                    assert np.array_equal(gb[k], gr[k]), f"replay {rep}: {k} differs"
+    for c, _ in ref + bat:
         c.close()
