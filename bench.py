@@ -31,6 +31,32 @@ HBM_PEAK_GBS = 8000.0
 # by the FP64 operations of its gfx950 implementation (46, 63, 38, 16, 9, 10
 # and 43 flops): 209 + 564 = 773.
 FLOPS_PER_EMS_PAIR = 773.0
+# What a pair executes: the bracketed Metropolis test replaces the two
+# logarithms and the log1p of the comparison (2 x 46 + 63 = 155 flops) by
+# cubic bounds (33 flops), so a pair that the bounds decide executes
+# 773 - 155 + 33 = 651 flops and a pair whose logarithms are evaluated
+# 773 + 33 = 806.
+# 1.1 % of the pairs of this workload's relaxed state reach the evaluated
+# comparison (0.06 % in the first steps from the lattice), counted with a
+# build of the sweep whose marginal counter counts every evaluation.
+FLOPS_PER_PAIR_BRACKETED = 651.0
+FLOPS_PER_PAIR_EVALUATED = 806.0
+EVALUATED_SHARE = 0.011
+FLOPS_PER_PAIR_EXECUTED = (FLOPS_PER_PAIR_BRACKETED * (1.0 - EVALUATED_SHARE)
+                           + FLOPS_PER_PAIR_EVALUATED * EVALUATED_SHARE)
+# Whole-step floor.  Compulsory HBM bytes per particle-step of the method in
+# FP64 (one pass over the state per stage): cells re-sorted every step (keys
+# and ids 32 B, gather of q, p, eps, rho, id 136 B), density and energy update
+# (q, eps, rho in; rho, eps out: 56 B), F/D sweep (q, rho, eps, p, id in;
+# p, eps out: 100 B), kicks, drift and force (236 B).
+HBM_BYTES_PER_PARTICLE_STEP = {"cells": 170.0, "density": 56.0, "fd": 100.0,
+                               "kick_drift_force": 236.0}
+# FP64 flops (FMA = 2) per pair term of the particle passes, with the
+# square root at its 16 flops: a density term 12 + 16, a force term 25 + 16,
+# a candidate distance test 9 (both passes gather over all 27 cells)
+FLOPS_DENSITY_TERM = 28.0
+FLOPS_FORCE_TERM = 41.0
+FLOPS_CANDIDATE = 9.0
 # compulsory HBM bytes of the F/D phase kernel: per staged particle entry its
 # list entry (4), p and eps read and written (64), q, rho, id read (36); per
 # pair its schedule entry (8)
@@ -50,9 +76,11 @@ def fd_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per F/D phase launch from the committed PMC record, or None
-    when the kernel sources changed since the counters were taken."""
+def traffic_record():
+    """The committed PMC record of the F/D sweep kernel (calibrated
+    FETCH_SIZE + WRITE_SIZE bytes of one launch, with the algorithmic bytes of
+    the same step), or None when the kernel sources changed since the
+    counters were taken."""
     try:
         with open(TRAFFIC_RECORD) as f:
             rec = json.load(f)
@@ -60,7 +88,41 @@ def measured_traffic():
         return None
     if rec.get("source_hash") != fd_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def measured_traffic():
+    """HBM bytes per F/D sweep launch from the committed record, or None."""
+    rec = traffic_record()
+    return None if rec is None else rec.get("bytes_per_launch")
+
+
+def step_floor(w, pairs_per_step, ms_per_step):
+    """Floor of the whole step from the two roofs: compulsory HBM bytes at
+    8 TB/s and algorithmic FP64 flops at 78.6 TFLOP/s, each as a fraction of
+    the measured step time; the larger floor is the one that binds."""
+    n = w.n
+    nc = [max(4, int(b / w.h) // 2 * 2) for b in w.box]
+    cand = 27.0 * n / (nc[0] * nc[1] * nc[2])         # candidates per particle
+    act = 2.0 * pairs_per_step / n                     # neighbours within h
+    ppp = pairs_per_step / n                           # F/D pairs per particle
+    flops = {"fd": ppp * FLOPS_PER_EMS_PAIR,
+             "density": act * FLOPS_DENSITY_TERM + cand * FLOPS_CANDIDATE,
+             "forces": act * FLOPS_FORCE_TERM + cand * FLOPS_CANDIDATE}
+    bytes_ = sum(HBM_BYTES_PER_PARTICLE_STEP.values())
+    f_tot = sum(flops.values())
+    hbm_ms = n * bytes_ / (HBM_PEAK_GBS * 1e9) * 1e3
+    valu_ms = n * f_tot / (FP64_VALU_PEAK_TFLOPS * 1e12) * 1e3
+    return {"hbm_bytes_per_particle_step": bytes_,
+            "hbm_bytes_by_stage": HBM_BYTES_PER_PARTICLE_STEP,
+            "fp64_flops_per_particle_step": f_tot,
+            "fp64_flops_by_stage": flops,
+            "candidates_per_particle": cand, "neighbours_per_particle": act,
+            "hbm_floor_ms": hbm_ms, "valu_floor_ms": valu_ms,
+            "hbm_frac": hbm_ms / ms_per_step, "valu_frac": valu_ms / ms_per_step,
+            "binds": "valu" if valu_ms >= hbm_ms else "hbm",
+            "t_floor_ms": max(hbm_ms, valu_ms),
+            "frac": max(hbm_ms, valu_ms) / ms_per_step}
 
 
 def linear_slope(y):
@@ -477,7 +539,11 @@ def main():
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "avg_launch_ms": avg_ms, "launches": fd_launches,
                 "pairs_per_launch": proposed / fd_launches,
-                "flops_per_pair": FLOPS_PER_EMS_PAIR}
+                "flops_per_pair": FLOPS_PER_EMS_PAIR,
+                "traffic_record": traffic_record(),
+                "flops_per_pair_executed": FLOPS_PER_PAIR_EXECUTED,
+                "frac_executed": achieved * FLOPS_PER_PAIR_EXECUTED / FLOPS_PER_EMS_PAIR
+                / FP64_VALU_PEAK_TFLOPS}
 
     cpu = None
     if not args.no_cpu_baseline and args.workload == WORKLOAD:
@@ -500,10 +566,12 @@ def main():
         "energy_drift": drift,
         "fd": {"pairs_per_step": proposed / args.steps,
                "staged_per_step_last": last_staged,
+               "pairs_per_step_last": last_pairs,
                "rejection_rate": (rej_e + rej_r) / max(proposed, 1),
                "rej_energy": rej_e, "rej_ratio": rej_r},
         "kernel_ms_per_step": breakdown,
         "roofline": roof,
+        "step_floor": step_floor(w, proposed / args.steps, 1e3 * elapsed / args.steps),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

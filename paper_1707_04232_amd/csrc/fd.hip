@@ -14,11 +14,13 @@
 // order between pairs sharing a particle gives the same result.
 //
 // GPU schedule.  The scheduling pass (schedule.hip) has stored, for every
-// task, its active pairs with their conflict level.  A workgroup of one wave
-// takes a range of consecutive tasks of one phase, stages in LDS the
+// task, its active pairs with their conflict level.  A workgroup (FD_WAVES
+// waves) takes a range of consecutive tasks of one phase, stages in LDS the
 // momenta and energies of the particles that take part in a pair, sorts the
 // range's pairs by level and applies the pairs of one level (which share no
-// particle) as parallel steps of 64 lanes.  Positions, densities and ids do
+// particle) as parallel steps over its lanes.  The number of level steps of
+// a batch is set by its deepest task (the longest chain of pairs that share
+// a particle, in round order), not by its size.  Positions, densities and ids do
 // not change during the sweep: positions and densities are packed once per
 // sweep into one (x, y, z, rho) record per particle and read from global
 // memory two level steps ahead of their use, which keeps the LDS footprint
@@ -175,7 +177,7 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
     int *s_maxlv = (int *)(s_poff + (FD_MAXTASKS + 1));
     int *s_ntot = s_maxlv + 1;                        // sorted entries of the window
 
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     const int64_t n = P.n;
     // phase of this range and its tasks
     int k_ph = 0;
@@ -187,18 +189,18 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
     const int64_t T0 = task_base + t0;
 
     // offsets of the range's tasks (R + 1 values) and of the phase
-    if (lane < R) {
-        s_eoff[lane] = pair_off[T0 + lane];
-        s_poff[lane] = part_off[T0 + lane];
+    if (tid < R) {
+        s_eoff[tid] = pair_off[T0 + tid];
+        s_poff[tid] = part_off[T0 + tid];
     }
-    if (lane == 0) {   // end of the range (R may be 64)
+    if (tid == 0) {   // end of the range (R may be FD_THREADS)
         s_eoff[R] = pair_off[T0 + R];
         s_poff[R] = part_off[T0 + R];
     }
     const uint32_t phase_p0 = part_off[task_base];
     __syncthreads();
     if (s_eoff[R] > pair_cap || s_poff[R] > part_cap) {   // schedule incomplete
-        if (lane == 0) atomicOr(err, ERR_PAIRCAP);
+        if (tid == 0) atomicOr(err, ERR_PAIRCAP);
         return;
     }
 
@@ -221,16 +223,16 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
         if (npr == 0) continue;
         const uint32_t rel0 = p_begin - phase_p0;   // list position of batch particle 0
         // ---- global indices of the particles that take part in a pair
-        for (int base = 0; base < np; base += FD_PPL * 64) {
+        for (int base = 0; base < np; base += FD_PPL * FD_THREADS) {
             uint32_t gl[FD_PPL];
 #pragma unroll
             for (int r = 0; r < FD_PPL; ++r) {
-                const int l = base + r * 64 + lane;
+                const int l = base + r * FD_THREADS + tid;
                 gl[r] = l < np ? part_list[p_begin + l] : 0u;
             }
 #pragma unroll
             for (int r = 0; r < FD_PPL; ++r) {
-                const int l = base + r * 64 + lane;
+                const int l = base + r * FD_THREADS + tid;
                 if (l < np) s_gidx[l] = gl[r];
             }
         }
@@ -241,11 +243,11 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
         int lo = 1;
         while (lo <= FD_NLVL) {
             int hi = FD_NLVL;
-            s_hist[lane + 1] = 0u;
-            if (lane == 0) *s_maxlv = 0;
+            if (tid < FD_NLVL) s_hist[tid + 1] = 0u;
+            if (tid == 0) *s_maxlv = 0;
             __syncthreads();
             if (oversized) {
-                for (int e = lane; e < npr; e += 64) {
+                for (int e = tid; e < npr; e += FD_THREADS) {
                     const int lv = (int)(pairs[e_begin + e] >> 50);
                     if (lv >= 1 && lv <= FD_NLVL) atomicAdd(&s_hist[lv], 1u);
                 }
@@ -258,19 +260,19 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
                 --hi;
                 hi = hi < lo ? lo : hi;   // one level (<= 64 pairs) always fits
                 __syncthreads();
-                s_hist[lane + 1] = 0u;
+                if (tid < FD_NLVL) s_hist[tid + 1] = 0u;
                 __syncthreads();
             }
             // counting sort of the batch's entries by level: histogram pass,
             // prefix, scatter pass.  Entries stay in registers (FD_EPL per
             // lane) between the passes unless the batch needs several passes.
-            constexpr int EP = FD_EPL * 64;
+            constexpr int EP = FD_EPL * FD_THREADS;
             uint64_t ebuf[FD_EPL];
             const bool one_pass = npr <= EP;
             for (int base = 0; base < npr; base += EP) {
 #pragma unroll
                 for (int r = 0; r < FD_EPL; ++r) {
-                    const int x = base + r * 64 + lane;
+                    const int x = base + r * FD_THREADS + tid;
                     ebuf[r] = x < npr ? pairs[e_begin + x] : 0ull;
                 }
 #pragma unroll
@@ -285,26 +287,26 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
                 }
             }
             __syncthreads();
-            {   // exclusive prefix over levels: lane x holds level x + 1
-                const uint32_t h = s_hist[lane + 1];
+            if (tid < 64) {   // exclusive prefix over levels (first wave): lane x holds level x + 1
+                const uint32_t h = s_hist[tid + 1];
                 uint32_t incl = h;
 #pragma unroll
                 for (int off = 1; off < 64; off <<= 1) {
                     const uint32_t v = (uint32_t)__shfl_up((int)incl, off);
-                    if (lane >= off) incl += v;
+                    if (tid >= off) incl += v;
                 }
-                s_off[lane + 1] = incl - h;
-                s_cur[lane + 1] = incl - h;
+                s_off[tid + 1] = incl - h;
+                s_cur[tid + 1] = incl - h;
                 const uint64_t nz = __ballot(h != 0u);
-                if (lane == 0) *s_maxlv = nz ? 64 - __clzll(nz) : 0;
-                if (lane == 63) *s_ntot = (int)incl;
+                if (tid == 0) *s_maxlv = nz ? 64 - __clzll(nz) : 0;
+                if (tid == 63) *s_ntot = (int)incl;
             }
             __syncthreads();
             for (int base = 0; base < npr; base += EP) {
                 if (!one_pass) {
 #pragma unroll
                     for (int r = 0; r < FD_EPL; ++r) {
-                        const int x = base + r * 64 + lane;
+                        const int x = base + r * FD_THREADS + tid;
                         ebuf[r] = x < npr ? pairs[e_begin + x] : 0ull;
                     }
                 }
@@ -329,18 +331,18 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
                 const int ntot = min(*s_ntot, CE);
                 double *wdraws = draws + 4 * (int64_t)e_begin;
                 constexpr int DPL = 4;   // entries per lane per pass: id loads in flight
-                for (int base = 0; base < ntot; base += DPL * 64) {
+                for (int base = 0; base < ntot; base += DPL * FD_THREADS) {
                     uint32_t pr[DPL], ida[DPL], idb[DPL];
 #pragma unroll
                     for (int r = 0; r < DPL; ++r) {
-                        const int e = base + r * 64 + lane;
+                        const int e = base + r * FD_THREADS + tid;
                         pr[r] = e < ntot ? s_sorted[e] : 0u;
                         ida[r] = e < ntot ? id[s_gidx[pr[r] & 0xFFFFu]] : 0u;
                         idb[r] = e < ntot ? id[s_gidx[pr[r] >> 16]] : 0u;
                     }
 #pragma unroll
                     for (int r = 0; r < DPL; ++r) {
-                        const int e = base + r * 64 + lane;
+                        const int e = base + r * FD_THREADS + tid;
                         if (e < ntot) {
                             uint32_t i0 = ida[r], i1 = idb[r];
                             if (i0 > i1) {
@@ -363,10 +365,10 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
                 // ---- stage momenta and energies (after the wait for the
                 //      range's predecessors, on the first batch)
                 wait();
-                for (int base = 0; base < np; base += FD_PPL * 64) {
+                for (int base = 0; base < np; base += FD_PPL * FD_THREADS) {
 #pragma unroll
                     for (int r = 0; r < FD_PPL; ++r) {
-                        const int l = base + r * 64 + lane;
+                        const int l = base + r * FD_THREADS + tid;
                         if (l < np) {
                             const int64_t g = s_gidx[l];
                             s_p[l] = state_load<COHERENT>(p + g);
@@ -384,10 +386,10 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
             // step k runs (the gathers only read LDS entries fixed above)
             const int top = *s_maxlv;
             const double *wdr = draws + 4 * (int64_t)e_begin;
-            // the step after (l, b): next 64 entries of level l, else the
-            // first entry of the next non-empty level (l > top: none)
+            // the step after (l, b): next FD_THREADS entries of level l, else
+            // the first entry of the next non-empty level (l > top: none)
             auto advance = [&](int &l, int &b) {
-                b += 64;
+                b += FD_THREADS;
                 while (l <= top && b >= (int)(s_off[l] + s_hist[l])) {
                     ++l;
                     if (l <= top) b = (int)s_off[l];
@@ -396,13 +398,13 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
             auto fetch = [&](int l, int b, int &li, int &lj, PairGeo &g) {
                 bool v = false;
                 if (l <= top) {
-                    const int e = b + lane;
+                    const int e = b + tid;
                     v = e < (int)(s_off[l] + s_hist[l]);
                     if (v) fd_gather(s_sorted, s_gidx, qrho, wdr, e, li, lj, g);
                 }
                 return v;
             };
-            int l0 = lo, b0 = (int)s_off[lo] - 64;
+            int l0 = lo, b0 = (int)s_off[lo] - FD_THREADS;
             advance(l0, b0);
             int l1 = l0, b1 = b0;
             advance(l1, b1);
@@ -434,7 +436,7 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
             if (!oversized) break;
         }
         // ---- write back momenta and energies
-        for (int l = lane; staged && l < np; l += 64) {
+        for (int l = tid; staged && l < np; l += FD_THREADS) {
             const int64_t g = s_gidx[l];
             state_store<COHERENT>(p + g, s_p[l]);
             state_store<COHERENT>(p + n + g, s_p[CP + l]);
@@ -449,7 +451,7 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
 __device__ __forceinline__ void fd_flush_counters(const FdCount &cnt, bool negeps,
                                                   unsigned long long *counters, uint32_t *err)
 {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;   // one flush per wave
     const uint32_t v0 = wave_sum_u32(cnt.proposed), v1 = wave_sum_u32(cnt.rej_energy);
     const uint32_t v2 = wave_sum_u32(cnt.rej_ratio), v3 = wave_sum_u32(cnt.marginal);
     const uint32_t v4 = wave_sum_u32(cnt.negeps);
@@ -482,12 +484,12 @@ __device__ __forceinline__ void fd_phase_body(const FdPhaseArgs &a, uint32_t blk
     fd_flush_counters(cnt, negeps, a.counters, a.A.err);
 }
 template <bool FAST>
-__global__ __launch_bounds__(64) void k_fd_phase(FdPhaseArgs a)
+__global__ __launch_bounds__(FD_THREADS) void k_fd_phase(FdPhaseArgs a)
 {
     fd_phase_body<FAST>(a, blockIdx.x);
 }
-SDPD_MULTI_KERNEL(k_fd_phase_fast_multi, FdPhaseArgs, fd_phase_body<true>, 64)
-SDPD_MULTI_KERNEL(k_fd_phase_gen_multi, FdPhaseArgs, fd_phase_body<false>, 64)
+SDPD_MULTI_KERNEL(k_fd_phase_fast_multi, FdPhaseArgs, fd_phase_body<true>, FD_THREADS)
+SDPD_MULTI_KERNEL(k_fd_phase_gen_multi, FdPhaseArgs, fd_phase_body<false>, FD_THREADS)
 
 // The whole sweep in one launch.  Its ranges, group by group (group 0 =
 // phase 0, then the groups of mutually disjoint phases; inside a group in
@@ -512,22 +514,23 @@ struct FdSweep {
 constexpr uint64_t kWaitTicks = 20ull * 100000000ull;   // 20 s
 
 template <bool FAST>
-__global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ Pp,
+__global__ __launch_bounds__(FD_THREADS) void k_fd_sweep(const DevParams *__restrict__ Pp,
                                                  const FdSweep *__restrict__ SW,
                                                  const uint32_t *__restrict__ order, FdArgs A,
                                                  uint32_t *work, uint32_t *epoch,
                                                  unsigned long long *counters)
 {
     extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ uint32_t s_item;
     const DevParams &P = *Pp;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     FdCount cnt = {0u, 0u, 0u, 0u, 0u};
     bool negeps = false;
     const uint32_t nitems = SW->nitems;
     for (;;) {
-        uint32_t it = 0u;
-        if (lane == 0) it = atomicAdd(work, 1u);
-        it = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)it, 0));
+        if (tid == 0) s_item = atomicAdd(work, 1u);
+        __syncthreads();
+        const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_item);
         if (it >= nitems) break;
         int g = 0;
         while (it >= SW->group_end[g]) ++g;
@@ -542,8 +545,8 @@ __global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ P
         const int R = (int)(t0 + tpw < ntasks ? tpw : ntasks - t0);
         const int64_t T0 = L.task_base[k_ph] + t0;
         int64_t cA = -1, cB = -1;
-        if (lane < R) {
-            const TaskCells tc = task_cells(P, T0 + lane);
+        if (tid < R) {
+            const TaskCells tc = task_cells(P, T0 + tid);
             cA = tc.A;
             cB = tc.slot == 0 ? -1 : tc.B;
         }
@@ -551,8 +554,8 @@ __global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ P
         auto wait = [&] {
             if (waited) return;
             waited = true;
-            if (g > 0) {
-                bool ready = lane >= R;
+            if (g > 0) {   // each wave polls the cells of its lanes' tasks
+                bool ready = tid >= R;
                 const uint64_t t_wait = wall_clock64();
                 for (;;) {
                     if (!ready) {
@@ -566,23 +569,25 @@ __global__ __launch_bounds__(64) void k_fd_sweep(const DevParams *__restrict__ P
                     }
                     if (__ballot(!ready) == 0ull) break;
                     if (wall_clock64() - t_wait > kWaitTicks) {
-                        if (lane == 0) atomicOr(A.err, ERR_STALL);
+                        if ((tid & 63) == 0) atomicOr(A.err, ERR_STALL);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(2);
                 }
             }
-            // no state access of the range moves above the wait (the state
-            // loads are themselves coherent, so no cache invalidation is
-            // needed)
+            // every wave has seen its cells released; no state access of the
+            // range moves above the wait (the state loads are themselves
+            // coherent, so no cache invalidation is needed)
+            __syncthreads();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         };
         fd_range<FAST, true>(P, L, b, lds, A, cnt, negeps, wait);
         // a range without pairs still orders its cells behind the predecessors
         wait();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_s_waitcnt(0);   // the state stores have completed
-        if (lane < R) {
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's state stores have completed
+        __syncthreads();                 // ... and those of the other waves
+        if (tid < R) {
             __hip_atomic_store(epoch + cA, (uint32_t)g + 1u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
             if (cB >= 0)
@@ -624,8 +629,8 @@ PhaseGeom phase_geom(int phase)
 // and pair entries per task, and their spread (standard deviation per task),
 // measured on jittered lattices; then a headroom factor on both capacities.
 // The own-cell phase gains from room for the heavy ranges (lattice cells of
-// 27 particles) while it stays under 20 KB, the LDS share of one of the 8
-// workgroups a CU holds at two waves per SIMD.
+// 27 particles) while it stays under 20 KB per wave, the LDS share of a
+// wave at two waves per SIMD.
 struct Allow {
     double mp, sp, me, se, room;
 };
@@ -635,7 +640,7 @@ constexpr Allow kAllow[4] = {
     {14.7, 10.0, 25.2, 20.0, 1.0},    // edge
     {6.7, 5.0, 5.4, 4.5, 1.0},        // corner
 };
-constexpr int kDefaultTasks[4] = {8, 8, 16, 24};
+constexpr int kDefaultTasks[4] = {8 * FD_WAVES, 8 * FD_WAVES, 16 * FD_WAVES, 24 * FD_WAVES};
 
 int round_up(double x, int q)
 {
@@ -813,9 +818,9 @@ static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, in
     timer_begin(c, TK_FD);
     const FdPhaseArgs args{c->dparams, L, fd_args(c, s, dt_fd), c->counters};
     const int rc = fd_fast(c) ? launch_or_record(c, k_fd_phase<true>, k_fd_phase_fast_multi,
-                                                 (unsigned)wg, 64, lds, args)
+                                                 (unsigned)wg, FD_THREADS, lds, args)
                               : launch_or_record(c, k_fd_phase<false>, k_fd_phase_gen_multi,
-                                                 (unsigned)wg, 64, lds, args);
+                                                 (unsigned)wg, FD_THREADS, lds, args);
     timer_end(c, TK_FD);
     return rc;
 }
@@ -938,7 +943,7 @@ int fd_prepare_sweep(sdpd_ctx *c)
         return rc;
     int per_cu = 0, cus = 0;
     const void *kern = fd_fast(c) ? (const void *)k_fd_sweep<true> : (const void *)k_fd_sweep<false>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, FD_THREADS, lds) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
             hipSuccess || per_cu < 1 || cus < 1) {
         (void)hipGetLastError();
@@ -1009,7 +1014,7 @@ int fd_launch_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
     if ((rc = launch_fill_u32(c, c->epoch, 0u, c->ncell + 1))) return rc;
     timer_begin(c, TK_FD);
     auto kern = fd_fast(c) ? k_fd_sweep<true> : k_fd_sweep<false>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)c->sweep_grid), dim3(64), c->sweep_lds, c->stream,
+    hipLaunchKernelGGL(kern, dim3((unsigned)c->sweep_grid), dim3(FD_THREADS), c->sweep_lds, c->stream,
                        c->dparams, (const FdSweep *)c->sweep, c->sweep_order, fd_args(c, s, dt_fd),
                        c->epoch + c->ncell, c->epoch, c->counters);
     timer_end(c, TK_FD);

@@ -31,7 +31,11 @@ constexpr int NMASK = 14;
 constexpr int NNB = 27;
 constexpr int OWN_NB = 13;
 constexpr int MAX_CAP = 64;
-constexpr int FD_MAXTASKS = 64;    // tasks per workgroup range of the F/D sweep
+// F/D sweep workgroups: FD_WAVES waves share one batch of tasks (the pairs
+// of a level are split over their lanes); at most one task per lane
+constexpr int FD_WAVES = 1;
+constexpr int FD_THREADS = 64 * FD_WAVES;
+constexpr int FD_MAXTASKS = FD_THREADS;   // tasks per workgroup range of the F/D sweep
 
 // Everything a kernel needs, by value.  Derived constants are computed once
 // on the host.

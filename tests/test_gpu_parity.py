@@ -272,7 +272,7 @@ def test_fd_sweep_tuning_does_not_change_results(sweep):
     gp, op, S, R = _fd_case((24, 20, 16), 1.5, 0.1, 0.05, 0, 0, 0.0)
     with sd().Context(gp) as ctx:
         before = ctx.get_tuning()
-        for bad in (dict(fd_tasks=(65, 1, 1, 1)), dict(lds_particles=(100, 0, 0, 0)),
+        for bad in (dict(fd_tasks=(129, 1, 1, 1)), dict(lds_particles=(100, 0, 0, 0)),
                     dict(lds_pairs=(0, 32, 0, 0)), dict(lds_particles=(65535,) * 4)):
             with pytest.raises(sdpd.SdpdError) as e:
                 ctx.tune(**bad)
