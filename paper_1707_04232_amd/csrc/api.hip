@@ -144,6 +144,11 @@ static void derive(const sdpd_params *P, const int nc[3], DevParams &d)
     d.m_f = (float)P->m;
     d.cW_f = (float)d.cW;
     d.cF_f = (float)d.cF;
+    d.inv_Cv_f = (float)d.inv_Cv;
+    d.d_c_f = (float)(d.kB * d.two_over_Cv);
+    d.inv_m_f = (float)d.inv_m;
+    d.b2_c_f = (float)d.b2_c;
+    d.kperp_c_f = (float)d.kperp_c;
     d.div_per = make_fastdiv((uint32_t)std::max<int64_t>(d.ncell / 8, 1));
     d.div_hx = make_fastdiv((uint32_t)std::max(nc[0] / 2, 1));
     d.div_hy = make_fastdiv((uint32_t)std::max(nc[1] / 2, 1));

@@ -141,13 +141,14 @@ struct FdArgs {
 
 // One task range: workgroup-range index b of the launch L (a range of
 // consecutive tasks of one of its phases), staged, sorted, drawn and applied
-// level by level.  FAST: the common case (EMS, Lucy kernel, zeta = 0) fixed
-// at compile time.
+// level by level.  K: 0 = general, 1 = the common case (EMS, Lucy kernel,
+// zeta = 0) fixed at compile time, 2 = that case with the FP32 proposal of
+// mixed precision.
 // wait() is called once, before the first access to momenta and energies:
 // everything before it (entries, lists, ids, positions, the draws) is fixed
 // during the sweep, so the level sort and the draws of a range overlap the
 // wait for its predecessors.
-template <bool FAST, bool COHERENT, class Wait>
+template <int K, bool COHERENT, class Wait>
 __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, int64_t b,
                                          unsigned char *lds, const FdArgs &A, FdCount &cnt,
                                          bool &negeps, Wait &wait)
@@ -418,7 +419,7 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
                 PairGeo g2 = {};
                 int li2 = 0, lj2 = 0;
                 const bool v2 = fetch(l2, b2, li2, lj2, g2);
-                if (v0) fd_pair<FAST>(P, dt, li0, lj0, g0, s_p, CP, s_eps, cnt, negeps);
+                if (v0) fd_pair<K != 0, K == 2>(P, dt, li0, lj0, g0, s_p, CP, s_eps, cnt, negeps);
                 __syncthreads();
                 g0 = g1;
                 li0 = li1;
@@ -473,23 +474,24 @@ struct FdPhaseArgs {
     FdArgs A;
     unsigned long long *counters;
 };
-template <bool FAST>
+template <int K>
 __device__ __forceinline__ void fd_phase_body(const FdPhaseArgs &a, uint32_t blk)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     FdCount cnt = {0u, 0u, 0u, 0u, 0u};
     bool negeps = false;
     auto no_wait = [] {};
-    fd_range<FAST, false>(*a.Pp, a.L, (int64_t)blk, lds, a.A, cnt, negeps, no_wait);
+    fd_range<K, false>(*a.Pp, a.L, (int64_t)blk, lds, a.A, cnt, negeps, no_wait);
     fd_flush_counters(cnt, negeps, a.counters, a.A.err);
 }
-template <bool FAST>
+template <int K>
 __global__ __launch_bounds__(FD_THREADS) void k_fd_phase(FdPhaseArgs a)
 {
-    fd_phase_body<FAST>(a, blockIdx.x);
+    fd_phase_body<K>(a, blockIdx.x);
 }
-SDPD_MULTI_KERNEL(k_fd_phase_fast_multi, FdPhaseArgs, fd_phase_body<true>, FD_THREADS)
-SDPD_MULTI_KERNEL(k_fd_phase_gen_multi, FdPhaseArgs, fd_phase_body<false>, FD_THREADS)
+SDPD_MULTI_KERNEL(k_fd_phase_gen_multi, FdPhaseArgs, fd_phase_body<0>, FD_THREADS)
+SDPD_MULTI_KERNEL(k_fd_phase_fast_multi, FdPhaseArgs, fd_phase_body<1>, FD_THREADS)
+SDPD_MULTI_KERNEL(k_fd_phase_mix_multi, FdPhaseArgs, fd_phase_body<2>, FD_THREADS)
 
 // The whole sweep in one launch.  Its ranges, group by group (group 0 =
 // phase 0, then the groups of mutually disjoint phases; inside a group in
@@ -513,7 +515,7 @@ struct FdSweep {
 };
 constexpr uint64_t kWaitTicks = 20ull * 100000000ull;   // 20 s
 
-template <bool FAST>
+template <int K>
 __global__ __launch_bounds__(FD_THREADS) void k_fd_sweep(const DevParams *__restrict__ Pp,
                                                  const FdSweep *__restrict__ SW,
                                                  const uint32_t *__restrict__ order, FdArgs A,
@@ -581,7 +583,7 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_sweep(const DevParams *__rest
             __syncthreads();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         };
-        fd_range<FAST, true>(P, L, b, lds, A, cnt, negeps, wait);
+        fd_range<K, true>(P, L, b, lds, A, cnt, negeps, wait);
         // a range without pairs still orders its cells behind the predecessors
         wait();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -677,24 +679,17 @@ void fd_default_tuning(sdpd_ctx *c)
     }
     if (c->max_lds > 65536) {
         // allow dynamic LDS beyond 64 KiB where the device has it
-        if (hipFuncSetAttribute((const void *)k_fd_phase<false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                c->max_lds) != hipSuccess ||
-            hipFuncSetAttribute((const void *)k_fd_phase<true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                c->max_lds) != hipSuccess ||
-            hipFuncSetAttribute((const void *)k_fd_sweep<false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                c->max_lds) != hipSuccess ||
-            hipFuncSetAttribute((const void *)k_fd_sweep<true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                c->max_lds) != hipSuccess ||
-            hipFuncSetAttribute((const void *)k_fd_phase_fast_multi,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                c->max_lds) != hipSuccess ||
-            hipFuncSetAttribute((const void *)k_fd_phase_gen_multi,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                c->max_lds) != hipSuccess) {
+        const void *kerns[] = {(const void *)k_fd_phase<0>, (const void *)k_fd_phase<1>,
+                               (const void *)k_fd_phase<2>, (const void *)k_fd_sweep<0>,
+                               (const void *)k_fd_sweep<1>, (const void *)k_fd_sweep<2>,
+                               (const void *)k_fd_phase_gen_multi,
+                               (const void *)k_fd_phase_fast_multi,
+                               (const void *)k_fd_phase_mix_multi};
+        bool ok = true;
+        for (const void *k : kerns)
+            ok = ok && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           c->max_lds) == hipSuccess;
+        if (!ok) {
             (void)hipGetLastError();
             c->max_lds = 65536;
         }
@@ -775,6 +770,13 @@ static bool fd_fast(const sdpd_ctx *c)
     return c->dp.fd == SDPD_FD_EMS && c->dp.kernel == SDPD_KERNEL_LUCY && c->dp.par_twice_perp;
 }
 
+// kernel variant: 0 general, 1 the common case, 2 the common case with the
+// FP32 proposal (mixed precision; other schemes keep the FP64 update)
+static int fd_kind(const sdpd_ctx *c)
+{
+    return fd_fast(c) ? (c->dp.mixed ? 2 : 1) : 0;
+}
+
 static FdArgs fd_args(const sdpd_ctx *c, const sdpd_state *s, double dt_fd)
 {
     FdArgs A;
@@ -817,10 +819,14 @@ static int launch_phases(sdpd_ctx *c, const sdpd_state *s, const int *phases, in
     if (lds > (size_t)c->max_lds) return SDPD_EINVAL;
     timer_begin(c, TK_FD);
     const FdPhaseArgs args{c->dparams, L, fd_args(c, s, dt_fd), c->counters};
-    const int rc = fd_fast(c) ? launch_or_record(c, k_fd_phase<true>, k_fd_phase_fast_multi,
-                                                 (unsigned)wg, FD_THREADS, lds, args)
-                              : launch_or_record(c, k_fd_phase<false>, k_fd_phase_gen_multi,
-                                                 (unsigned)wg, FD_THREADS, lds, args);
+    const int kind = fd_kind(c);
+    const int rc =
+        kind == 2 ? launch_or_record(c, k_fd_phase<2>, k_fd_phase_mix_multi, (unsigned)wg,
+                                     FD_THREADS, lds, args)
+        : kind == 1 ? launch_or_record(c, k_fd_phase<1>, k_fd_phase_fast_multi, (unsigned)wg,
+                                       FD_THREADS, lds, args)
+                    : launch_or_record(c, k_fd_phase<0>, k_fd_phase_gen_multi, (unsigned)wg,
+                                       FD_THREADS, lds, args);
     timer_end(c, TK_FD);
     return rc;
 }
@@ -942,7 +948,9 @@ int fd_prepare_sweep(sdpd_ctx *c)
                                   hipMemcpyHostToDevice))))
         return rc;
     int per_cu = 0, cus = 0;
-    const void *kern = fd_fast(c) ? (const void *)k_fd_sweep<true> : (const void *)k_fd_sweep<false>;
+    const int kind = fd_kind(c);
+    const void *kern = kind == 2 ? (const void *)k_fd_sweep<2>
+                       : kind == 1 ? (const void *)k_fd_sweep<1> : (const void *)k_fd_sweep<0>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, FD_THREADS, lds) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
             hipSuccess || per_cu < 1 || cus < 1) {
@@ -1013,7 +1021,8 @@ int fd_launch_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
     // epochs of the cells and the range counter start at zero
     if ((rc = launch_fill_u32(c, c->epoch, 0u, c->ncell + 1))) return rc;
     timer_begin(c, TK_FD);
-    auto kern = fd_fast(c) ? k_fd_sweep<true> : k_fd_sweep<false>;
+    const int kind = fd_kind(c);
+    auto kern = kind == 2 ? k_fd_sweep<2> : kind == 1 ? k_fd_sweep<1> : k_fd_sweep<0>;
     hipLaunchKernelGGL(kern, dim3((unsigned)c->sweep_grid), dim3(FD_THREADS), c->sweep_lds, c->stream,
                        c->dparams, (const FdSweep *)c->sweep, c->sweep_order, fd_args(c, s, dt_fd),
                        c->epoch + c->ncell, c->epoch, c->counters);

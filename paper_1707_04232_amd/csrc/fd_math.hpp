@@ -65,6 +65,7 @@ __device__ __forceinline__ void pair_draws(const DevParams &P, uint32_t step, ui
 // alpha = 1 + e and 1 - alpha^2 = -e (2 + e), both without cancellation.
 struct Coef {
     double al_par, al_perp, b2_par, b2_perp;
+    double b_par, b_perp;   // square roots of b2 (set by fd_coef_f32 only)
 };
 
 // When zeta = 0 the parallel friction is exactly twice the perpendicular one,
@@ -89,6 +90,57 @@ __device__ __forceinline__ Coef fd_coef(const DevParams &P, double kpar, double 
     r.al_perp = 1.0 + e_perp;
     r.b2_par = -s * e_par * (2.0 + e_par);
     r.b2_perp = -s * e_perp * (2.0 + e_perp);
+    return r;
+}
+
+// ---------------------------------------------------------------- FP32 proposal
+// Mixed precision: the geometry and the proposal coefficients e = alpha - 1
+// and b of eq. (proposal) in FP32 (hardware reciprocal, square root and
+// exponential), for the forward and the reverse move alike.  The proposal
+// v' = alpha v + b G, the energies, Delta and the Metropolis log-ratio of
+// eq. (metropolis-ratio) stay FP64 and use exactly these coefficients: alpha
+// = 1 + e and b are FP32 values promoted, b^2 is formed in FP64 from b (an
+// exact square), so the ratio is the exact one of the FP32-defined proposal.
+
+// expm1(x): Taylor polynomial to x^8 for |x| < 1/2 (its tail is below
+// 2^-26 |x| there), exp(x) - 1 otherwise (no cancellation for |x| >= 1/2)
+__device__ __forceinline__ float expm1_f32(float x)
+{
+    float p = 2.4801587e-05f;        // 1/8!
+    p = fmaf(p, x, 1.9841270e-04f);  // 1/7!
+    p = fmaf(p, x, 1.3888889e-03f);  // 1/6!
+    p = fmaf(p, x, 8.3333333e-03f);  // 1/5!
+    p = fmaf(p, x, 4.1666668e-02f);  // 1/4!
+    p = fmaf(p, x, 1.6666667e-01f);  // 1/3!
+    p = fmaf(p, x, 0.5f);
+    const float small = fmaf(p * x, x, x);
+    const float big = __expf(x) - 1.0f;
+    return fabsf(x) < 0.5f ? small : big;
+}
+
+// the coefficients at energies (ei, ej), EMS with Lucy's kernel and zeta = 0
+// (kpar = 2 kperp, so e_par = e_perp (2 + e_perp)); kperp in FP32
+__device__ __forceinline__ Coef fd_coef_f32(const DevParams &P, float kperp, double ei, double ej,
+                                            float dt)
+{
+    const float Ti = (float)ei * P.inv_Cv_f, Tj = (float)ej * P.inv_Cv_f;
+    const float inv_Ts = __builtin_amdgcn_rcpf(Ti + Tj);
+    const float Tred = Ti * Tj * inv_Ts;
+    const float d = P.d_c_f * Tred * inv_Ts;
+    const float omd = 1.0f - d;
+    const float c = -2.0f * dt * P.inv_m_f * omd;
+    const float e_perp = expm1_f32(c * kperp);
+    const float e_par = e_perp * (2.0f + e_perp);
+    const float s = P.b2_c_f * Tred * __builtin_amdgcn_rcpf(omd);
+    const float bp = __builtin_amdgcn_sqrtf(-s * e_par * (2.0f + e_par));
+    const float bq = __builtin_amdgcn_sqrtf(-s * e_perp * (2.0f + e_perp));
+    Coef r;
+    r.al_par = 1.0 + (double)e_par;
+    r.al_perp = 1.0 + (double)e_perp;
+    r.b_par = (double)bp;
+    r.b_perp = (double)bq;
+    r.b2_par = r.b_par * r.b_par;
+    r.b2_perp = r.b_perp * r.b_perp;
     return r;
 }
 
@@ -130,28 +182,48 @@ __device__ __forceinline__ double log1p_cubic(double x)
 constexpr double kLazyMargin = 2e-9;
 
 // One pair update; li has the smaller id.  Momenta (x, y, z planes at
-// stride ps) and energies are LDS-resident.
-template <bool FAST>
+// stride ps) and energies are LDS-resident.  MIX (with FAST only): the
+// geometry and the proposal coefficients in FP32 (fd_coef_f32).
+template <bool FAST, bool MIX = false>
 __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
                                         int lj, const PairGeo &pg, double *s_p, int ps,
                                         double *s_eps, FdCount &cnt, bool &negeps)
 {
 #pragma clang fp contract(fast)
+    static_assert(!MIX || FAST, "the FP32 proposal covers EMS, Lucy's kernel, zeta = 0");
     // geometry (Sec. 2.1.1): r_ij, e_ij, F_ij
     const double dx = min_image(pg.xi - pg.xj, P.box[0], P.half_box[0]);
     const double dy = min_image(pg.yi - pg.yj, P.box[1], P.half_box[1]);
     const double dz = min_image(pg.zi - pg.zj, P.box[2], P.half_box[2]);
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const double inv_r = fast_rsq(r2);
-    const double r = r2 * inv_r;
-    const double ex = dx * inv_r, ey = dy * inv_r, ez = dz * inv_r;
-    const double x = r * P.inv_h, t = 1.0 - x;
-    double F;
-    if (FAST || P.kernel == SDPD_KERNEL_LUCY) F = P.cF * (t * t);
-    else F = x <= 0.5 ? P.cF * (2.0 - 3.0 * x) : P.cF * P.h * (t * t) * inv_r;
-    // kappa^theta of Sec. 2.2.2
-    const double kfac = F * fast_rcp(pg.rho_i * pg.rho_j);
-    const double kpar = P.kpar_c * kfac, kperp = P.kperp_c * kfac;
+    double ex, ey, ez, kpar = 0.0, kperp = 0.0;
+    float kperp_f = 0.0f;
+    if (MIX) {
+        const float xf = (float)dx, yf = (float)dy, zf = (float)dz;
+        const float r2 = xf * xf + yf * yf + zf * zf;
+        const float inv_r = __builtin_amdgcn_rsqf(r2);
+        const float t = 1.0f - r2 * inv_r * P.inv_h_f;
+        ex = (double)(xf * inv_r);
+        ey = (double)(yf * inv_r);
+        ez = (double)(zf * inv_r);
+        // kappa_perp of Sec. 2.2.2 with Lucy's F
+        kperp_f = P.kperp_c_f * (P.cF_f * (t * t)) *
+                  __builtin_amdgcn_rcpf((float)(pg.rho_i * pg.rho_j));
+    } else {
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double inv_r = fast_rsq(r2);
+        const double r = r2 * inv_r;
+        ex = dx * inv_r;
+        ey = dy * inv_r;
+        ez = dz * inv_r;
+        const double x = r * P.inv_h, t = 1.0 - x;
+        double F;
+        if (FAST || P.kernel == SDPD_KERNEL_LUCY) F = P.cF * (t * t);
+        else F = x <= 0.5 ? P.cF * (2.0 - 3.0 * x) : P.cF * P.h * (t * t) * inv_r;
+        // kappa^theta of Sec. 2.2.2
+        const double kfac = F * fast_rcp(pg.rho_i * pg.rho_j);
+        kpar = P.kpar_c * kfac;
+        kperp = P.kperp_c * kfac;
+    }
 
     const double ei = s_eps[li], ej = s_eps[lj];
     const double vx = (s_p[li] - s_p[lj]) * P.inv_m;
@@ -161,8 +233,10 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
     const double G[3] = {pg.G0, pg.G1, pg.G2};
 
     // proposal, eq. (proposal): v' = A(v) v + B(v) G, B = (2/m) zeta^theta P^theta
-    const Coef f = fd_coef<FAST>(P, kpar, kperp, ei, ej, dt);
-    const double b_par = fd_sqrt(f.b2_par), b_perp = fd_sqrt(f.b2_perp);
+    const Coef f = MIX ? fd_coef_f32(P, kperp_f, ei, ej, (float)dt)
+                       : fd_coef<FAST>(P, kpar, kperp, ei, ej, dt);
+    const double b_par = MIX ? f.b_par : fd_sqrt(f.b2_par);
+    const double b_perp = MIX ? f.b_perp : fd_sqrt(f.b2_perp);
     const double vpar = vx * ex + vy * ey + vz * ez;
     const double Gpar = G[0] * ex + G[1] * ey + G[2] * ez;
     const double vqx = vx - vpar * ex, vqy = vy - vpar * ey, vqz = vz - vpar * ez;
@@ -191,7 +265,8 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
         } else if (FAST || P.fd == SDPD_FD_EMS) {
             // reverse move from v' at the proposed energies, eq. (metropolis-ratio)
             const double ei2 = ei - delta, ej2 = ej - delta;
-            const Coef g = fd_coef<FAST>(P, kpar, kperp, ei2, ej2, dt);
+            const Coef g = MIX ? fd_coef_f32(P, kperp_f, ei2, ej2, (float)dt)
+                               : fd_coef<FAST>(P, kpar, kperp, ei2, ej2, dt);
             const double wpar = vpar - g.al_par * npar;
             const double wqx = vqx - g.al_perp * nqx;
             const double wqy = vqy - g.al_perp * nqy;

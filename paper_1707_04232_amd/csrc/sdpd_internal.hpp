@@ -63,6 +63,9 @@ struct DevParams {
     int mixed;
     float cell_f[3];        // cell edge lengths box / nc
     float h_f, h2_f, inv_h_f, m_f, cW_f, cF_f;
+    // ... and of the F/D proposal coefficients (FP32 proposal, EMS with
+    // Lucy's kernel and zeta = 0)
+    float inv_Cv_f, d_c_f, inv_m_f, b2_c_f, kperp_c_f;
     // task numbering of the F/D schedule: tasks per inter-cell phase
     // (ncell / 8) and the half extents nc[0] / 2, nc[1] / 2
     FastDiv div_per, div_hx, div_hy;

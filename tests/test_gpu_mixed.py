@@ -1,5 +1,6 @@
 """Mixed precision (FP32 density and forces from cell-relative positions,
-everything else FP64) against the FP64 oracle on a 64^3 jittered lattice
+FP32 geometry and proposal coefficients in the F/D update, everything else
+FP64) against the FP64 oracle on a 64^3 jittered lattice
 with C_v = 10, T = 1 (the small box of the 8M-particle mixed-precision
 workload), and against the FP64 GPU path over a short trajectory.
 
@@ -65,17 +66,33 @@ def test_mixed_density_forces_vs_oracle():
     assert np.abs(G["f"].sum(axis=1)).max() < 1e-6 * term_max * len(eps)
 
 
-def test_mixed_fd_sweep_vs_oracle():
-    """The F/D sweep of the mixed path is FP64; what it takes from the FP32
-    passes is the pair set (r < h decided in FP32) and the densities in the
-    friction coefficients.  On a lattice with jitter 0.01 every pair distance
-    is at least 0.016 away from h (the sixth neighbour shell lies at
-    sqrt(6) = 2.449, the seventh at 2.83), far beyond the ~1e-6 FP32 error,
-    so both sides hold the same pairs; the oracle is given the GPU's
-    densities.  Then the sweep must agree element by element at 1e-10."""
+MIXED_FD_CASES = [((16, 12, 12), 9), ((10, 10, 10), 10)]
+
+
+@pytest.mark.parametrize("dims,step", MIXED_FD_CASES, ids=["16x12x12", "10"])
+def test_mixed_fd_sweep_vs_oracle(dims, step):
+    """The mixed path's F/D sweep computes the geometry and the proposal
+    coefficients (alpha, b of eq. (proposal)) in FP32 and everything else in
+    FP64, with the Metropolis ratio of eq. (metropolis-ratio) evaluated for
+    exactly those coefficients; the oracle is FP64 throughout.
+
+    Pair set: on a lattice with jitter 0.01 every pair distance is at least
+    0.016 away from h (the sixth neighbour shell lies at sqrt(6) = 2.449,
+    the seventh at 2.83), far beyond the ~1e-6 FP32 error of r, so both sides
+    hold the same pairs; the oracle is given the GPU's densities.
+
+    Decisions: the FP32 coefficients carry a few ulp (~3e-7) of relative
+    error, which moves log-ratio a (a sum of O(1) terms) by ~1e-6 and the
+    energy bound by ~1e-7 of the energies.  The cases (box, step) are chosen
+    so that no decision of the oracle lies within 2e-5 of its boundary
+    (checked below on the oracle's log), so every decision must agree.
+
+    State: a pair update moves v by (alpha - 1) v + b G; the FP32 error of
+    the coefficients puts ~3e-7 of that on it.  A particle takes part in
+    ~65 pairs, so p is off by at most ~2e-5 of the momentum scale and eps
+    by less; the test asks 2e-5 of the largest value for both."""
     sdpd = sd()
-    dims = (24, 20, 16)
-    say("mixed F/D sweep vs oracle", dims)
+    say("mixed F/D sweep vs oracle", dims, "step", step)
     q, p, eps, ids = lattice_state(dims, Cv=1.5, T=0.1, jitter=0.01)
     box = tuple(float(d) for d in dims)
     g = sdpd.SdpdParams(n=len(eps), box=box, Cv=1.5, prec=sdpd.MIXED, dt=0.05)
@@ -83,7 +100,7 @@ def test_mixed_fd_sweep_vs_oracle():
     with sdpd.Context(g) as ctx:
         ctx.prepare(S)
         rho_gpu = S.rho.cpu().numpy().copy()
-        st = ctx.fd_metropolis(S, step=2)
+        st = ctx.fd_metropolis(S, step=step)
         G = S.to_numpy()
     P = O.OracleParams(n=len(eps), box=box, Cv=1.5, dt=0.05)
     R = O.State.from_arrays(q, p, eps, ids)
@@ -98,7 +115,20 @@ def test_mixed_fd_sweep_vs_oracle():
     assert r.max() < P.h - 0.01
     say(f"rho: mixed vs FP64 {np.abs(rho_gpu - R.rho).max():.2e}")
     R.rho[:] = rho_gpu
-    PU.sweep_and_compare(P, R, 2, G, st, 1e-10, say)
+    R0 = R.copy()
+    rc, ost, olog = O.fd_sweep(P, R, step, log=True)
+    assert rc == 0
+    evaluated = olog["decision"] != 1
+    margin = np.abs(olog["a_minus_lnU"][evaluated]).min()
+    gap = np.abs(olog["bound_gap"]).min() / np.abs(R0.eps).max()
+    say(f"closest decision: |a - ln U| {margin:.2e}, energy bound {gap:.2e}")
+    assert margin > 2e-5 and gap > 1e-4, "case no longer clear of the decision boundaries"
+    for k in ("proposed", "rej_energy", "rej_ratio"):
+        assert st[k] == ost[k], (k, st[k], ost[k])
+    ep = PU.rel_masked(G["p"], R.p, np.ones(len(eps), bool))
+    ee = PU.rel_masked(G["eps"], R.eps, np.ones(len(eps), bool))
+    say(f"p rel err {ep:.2e}, eps rel err {ee:.2e}, rejections {st['rej_ratio']}")
+    assert ep <= 2e-5 and ee <= 2e-5
 
 
 def test_mixed_trajectory_vs_oracle():
