@@ -258,9 +258,24 @@ def replicas_bench(args):
         torch.cuda.synchronize()
         tuned = {"fd_tasks": tuned, "seconds": time.perf_counter() - t0}
         print(f"# autotuned {tuned}", file=sys.stderr, flush=True)
+    if args.lds_budget:
+        # every box's LDS capacities scaled down (per phase class, keeping the
+        # proportion of particles to pair entries) to fit the budget, so that
+        # one persistent sweep launch keeps its workgroups per CU
+        budget = int(args.lds_budget * 1024)
+        for ctx in ctxs:
+            t = ctx.get_tuning()
+            cps, ces = list(t["lds_particles"]), list(t["lds_pairs"])
+            for k in range(4):
+                f = min(1.0, (budget - 1320) / (36.0 * cps[k] + 4.0 * ces[k]))
+                cps[k] = max(128, int(cps[k] * f) // 16 * 16)
+                ces[k] = max(64, int(ces[k] * f) // 64 * 64)
+            ctx.tune(t["fd_tasks"], cps, ces)
+        tuned = dict(tuned or {}, lds_budget_kib=args.lds_budget)
     t0 = time.perf_counter()
-    B = sdpd.Batch(ctxs, states, layout=sdpd.BATCH_FUSED if args.batch_layout == "fused"
-                   else sdpd.BATCH_GRAPHS, parts=args.batch_parts)
+    B = sdpd.Batch(ctxs, states, layout={"fused": sdpd.BATCH_FUSED, "flow": sdpd.BATCH_FUSED_FLOW,
+                                         "graphs": sdpd.BATCH_GRAPHS}[args.batch_layout],
+                   parts=args.batch_parts)
     t_capture = time.perf_counter() - t0
     B.run(0, args.warmup)
     torch.cuda.synchronize()
@@ -420,17 +435,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--streams", type=int, default=32,
                     help="streams of the replicas workload (at most 32)")
-    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="replicas workload: keep the default tuning instead of running the "
-                         "library's autotuner per box size class")
-    ap.add_argument("--batch-layout", choices=("fused", "graphs"), default="fused",
-                    help="replicas workload: one launch per stage for all boxes (fused), or "
+    ap.add_argument("--autotune", action="store_true",
+                    help="replicas workload: run the library's autotuner per box size class "
+                         "(it times single-box sweeps; the default tuning serves the batch "
+                         "better)")
+    ap.add_argument("--batch-layout", choices=("fused", "flow", "graphs"), default="fused",
+                    help="replicas workload: one launch per stage for all boxes (fused), the "
+                         "same with one persistent F/D sweep launch for all boxes (flow), or "
                          "each box's launches captured into graphs per stream (graphs)")
     ap.add_argument("--tasks", default="",
                     help="replicas workload: tasks per workgroup of the four F/D phase classes "
                          "for every box, e.g. 4,4,8,12 (instead of the autotuner)")
     ap.add_argument("--lds-scale", type=float, default=1.0,
                     help="replicas workload with --tasks: scale of the LDS capacities")
+    ap.add_argument("--lds-budget", type=float, default=0.0,
+                    help="replicas workload: scale every box's F/D LDS capacities down to at "
+                         "most this many KiB per workgroup (after any autotuning)")
     ap.add_argument("--batch-parts", type=int, default=0,
                     help="replicas workload, fused layout: parts of the batch, each on its own "
                          "stream (0 = the library's choice)")

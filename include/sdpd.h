@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SDPD_ABI_VERSION 7
+#define SDPD_ABI_VERSION 8
 
 typedef enum {
     SDPD_OK = 0,
@@ -311,13 +311,20 @@ int sdpd_batch_create(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
  *                      its own graph and stream, which run side by side;
  *                      ~50 launches per part and step for any number of
  *                      boxes.  Boxes of any size, precision and scheme.
+ *   SDPD_BATCH_FUSED_FLOW  the fused layout with the F/D sweeps of a part's
+ *                      boxes in one persistent launch (their task ranges,
+ *                      group by group over all boxes, handed out by one
+ *                      counter; a range waits only for its own box's earlier
+ *                      groups, on per-cell epochs), instead of one launch
+ *                      per group of commuting phases;
  *   SDPD_BATCH_GRAPHS  each box's own launch sequence captured: one graph per
  *                      stream, or one graph forking to the boxes' streams
  *                      (see sdpd_batch_create above);
  *   SDPD_BATCH_AUTO    the fused layout (what sdpd_batch_create uses).
  * Results are identical bit for bit in every layout.  sdpd_batch_layout
  * returns the layout in use (SDPD_EINVAL for NULL).                         */
-enum { SDPD_BATCH_AUTO = 0, SDPD_BATCH_FUSED = 1, SDPD_BATCH_GRAPHS = 2 };
+enum { SDPD_BATCH_AUTO = 0, SDPD_BATCH_FUSED = 1, SDPD_BATCH_GRAPHS = 2,
+       SDPD_BATCH_FUSED_FLOW = 3 };
 int sdpd_batch_create_layout(sdpd_ctx *const *ctxs, const sdpd_state *states, int nbox,
                              int layout, int parts, sdpd_batch **out);
 int sdpd_batch_layout(const sdpd_batch *batch);

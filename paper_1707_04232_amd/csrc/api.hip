@@ -283,6 +283,13 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
             hipSuccess || lds <= 0)
             lds = 65536;
         c->max_lds = lds;
+        // the LDS share of one sweep workgroup when the CU holds two waves
+        // per SIMD (eight waves per CU); the default capacities stay within it
+        int per_cu = 0;
+        if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                  c->device) != hipSuccess || per_cu <= 0)
+            per_cu = 65536;
+        c->lds_share = std::max(per_cu / 8 * FD_WAVES, 4096);
     }
     fd_default_tuning(c);
     // schedule capacity: 64 pairs per particle (a jittered lattice has ~39),

@@ -46,6 +46,8 @@ struct FusedLaunch {
     size_t lds = 0;
     void *tab = nullptr;   // device: argument structs of the participating boxes
     uint2 *wg = nullptr;   // device: (slot in tab, workgroup of that box)
+    bool is_flow = false;  // instead: the one-launch F/D sweep of the boxes
+    sdpd::FlowSweep flow;
 };
 
 // boxes advanced by one sequence of multi-box launches on one stream
@@ -62,6 +64,7 @@ struct FusedPart {
 
 struct sdpd_batch {
     int layout = SDPD_BATCH_GRAPHS;
+    bool flow = false;   // fused layout with one sweep launch for all boxes of a part
     std::vector<FusedPart> parts;
     unsigned long long **dsteps = nullptr;   // device: each box's step-index word
     std::vector<sdpd_ctx *> ctx;
@@ -97,6 +100,7 @@ static void batch_free(sdpd_batch *b)
         for (FusedLaunch &f : p.launches) {
             if (f.tab) (void)hipFree(f.tab);
             if (f.wg) (void)hipFree(f.wg);
+            fd_flow_free(f.flow);
         }
         if (p.exec) (void)hipGraphExecDestroy(p.exec);
         if (p.graph) (void)hipGraphDestroy(p.graph);
@@ -138,8 +142,10 @@ static int build_fused(sdpd_batch *b, int nparts)
         sdpd_ctx *c = b->ctx[i];
         c->rec = &recs[i];
         c->fd_per_group = 1;
+        c->fd_record_flow = b->flow ? 1 : 0;
         for (int k = 0; k < b->theta && !rc; ++k) rc = enqueue_step(c, &b->st[i], (uint64_t)k, false);
         c->fd_per_group = 0;
+        c->fd_record_flow = 0;
         c->rec = nullptr;
     }
     if (rc) return rc;
@@ -162,19 +168,38 @@ static int build_fused(sdpd_batch *b, int nparts)
         for (int i : part.boxes) maxlen = std::max(maxlen, recs[i].size());
         for (size_t pos = 0; pos < maxlen; ++pos) {
             // boxes with the same kernel at this position share one launch
-            std::vector<MultiKernel> kinds;
+            using Key = std::pair<MultiKernel, int>;   // (kernel, kind of a flow sweep)
+            std::vector<Key> kinds;
             for (int i : part.boxes)
-                if (pos < recs[i].size() &&
-                    std::find(kinds.begin(), kinds.end(), recs[i][pos].multi) == kinds.end())
-                    kinds.push_back(recs[i][pos].multi);
-            for (MultiKernel kind : kinds) {
+                if (pos < recs[i].size()) {
+                    const Key k(recs[i][pos].multi, recs[i][pos].flow_kind);
+                    if (std::find(kinds.begin(), kinds.end(), k) == kinds.end()) kinds.push_back(k);
+                }
+            for (const Key &key : kinds) {
+                const MultiKernel kind = key.first;
+                if (key.second >= 0) {   // the boxes' F/D sweeps as one launch
+                    std::vector<sdpd_ctx *> cs;
+                    std::vector<const RecordedLaunch *> rs;
+                    for (int i : part.boxes)
+                        if (pos < recs[i].size() && recs[i][pos].flow_kind == key.second) {
+                            cs.push_back(b->ctx[i]);
+                            rs.push_back(&recs[i][pos]);
+                        }
+                    part.launches.push_back(FusedLaunch());   // freed with the batch from here on
+                    FusedLaunch &g = part.launches.back();
+                    g.is_flow = true;
+                    if ((rc = fd_flow_build(cs, rs, g.flow))) return rc;
+                    continue;
+                }
                 FusedLaunch f;
                 f.multi = kind;
                 std::vector<unsigned char> tab;
                 std::vector<uint2> wg;
                 unsigned slot = 0;
                 for (int i : part.boxes) {
-                    if (pos >= recs[i].size() || recs[i][pos].multi != kind) continue;
+                    if (pos >= recs[i].size() || recs[i][pos].multi != kind ||
+                        recs[i][pos].flow_kind >= 0)
+                        continue;
                     const RecordedLaunch &r = recs[i][pos];
                     if (f.block && r.block != f.block) return SDPD_EINVAL;
                     f.block = r.block;
@@ -214,10 +239,18 @@ static int capture_fused(sdpd_batch *b)
             return SDPD_EHIP;
         if (hipStreamBeginCapture(part.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return SDPD_EHIP;
-        for (const FusedLaunch &f : part.launches)
+        int rc = SDPD_OK;
+        for (const FusedLaunch &f : part.launches) {
+            if (f.is_flow) {
+                const int r = fd_flow_launch(f.flow, part.stream);
+                rc = rc ? rc : r;
+                continue;
+            }
             hipLaunchKernelGGL(f.multi, dim3(f.nblocks), dim3(f.block), f.lds, part.stream,
                                (const void *)f.tab, (const uint2 *)f.wg);
-        int rc = check_hip(hipGetLastError());
+        }
+        const int rl = check_hip(hipGetLastError());
+        rc = rc ? rc : rl;
         const hipError_t ec = hipStreamEndCapture(part.stream, &part.graph);
         if (!rc && ec != hipSuccess) rc = SDPD_EHIP;
         if (!rc && hipGraphInstantiate(&part.exec, part.graph, nullptr, nullptr, 0) != hipSuccess)
@@ -245,7 +278,7 @@ int sdpd_batch_create_layout(sdpd_ctx *const *ctxs, const sdpd_state *states, in
 {
     if (!out || !ctxs || !states || nbox < 1) return SDPD_EINVAL;
     *out = nullptr;
-    if (layout < SDPD_BATCH_AUTO || layout > SDPD_BATCH_GRAPHS) return SDPD_EINVAL;
+    if (layout < SDPD_BATCH_AUTO || layout > SDPD_BATCH_FUSED_FLOW) return SDPD_EINVAL;
     const int theta = ctxs[0] ? ctxs[0]->prm.fd_every : 0;
     for (int k = 0; k < nbox; ++k) {
         const sdpd_ctx *c = ctxs[k];
@@ -287,7 +320,8 @@ int sdpd_batch_create_layout(sdpd_ctx *const *ctxs, const sdpd_state *states, in
         return rc;
     }
     if (layout != SDPD_BATCH_GRAPHS) {
-        b->layout = SDPD_BATCH_FUSED;
+        b->layout = layout == SDPD_BATCH_FUSED_FLOW ? SDPD_BATCH_FUSED_FLOW : SDPD_BATCH_FUSED;
+        b->flow = b->layout == SDPD_BATCH_FUSED_FLOW;
         rc = build_fused(b, parts > 0 ? parts : std::min(hw_queues(), 16));
         if (!rc) rc = capture_fused(b);
         if (rc) {
@@ -371,7 +405,7 @@ int sdpd_batch_run(sdpd_batch *b, uint64_t step0, int nsteps)
         if (b->ctx[k]->tune_gen != b->gen[k]) return SDPD_EINVAL;   // retuned since the capture
     if (nsteps == 0) return SDPD_OK;
     int rc;
-    if (b->layout == SDPD_BATCH_FUSED) {
+    if (b->layout != SDPD_BATCH_GRAPHS) {
         // the boxes' earlier work first, then everything on the batch's stream
         for (size_t i = 0; i < b->streams.size(); ++i) {
             if ((rc = check_hip(hipEventRecord(b->ready[i], b->streams[i])))) return rc;

@@ -515,6 +515,74 @@ struct FdSweep {
 };
 constexpr uint64_t kWaitTicks = 20ull * 100000000ull;   // 20 s
 
+// One range of the one-launch sweep: range b of group g, waiting until the
+// cells of its tasks have epoch g and setting them to g + 1 afterwards.
+template <int K>
+__device__ __forceinline__ void fd_flow_range(const DevParams &P, const FdLaunch &L, int g,
+                                              int64_t b, const FdArgs &A, uint32_t *epoch,
+                                              unsigned char *lds, FdCount &cnt, bool &negeps)
+{
+    const int tid = threadIdx.x;
+    // the range's tasks (as fd_range finds them)
+    int k_ph = 0;
+    while (k_ph + 1 < L.nph && b >= L.wg_end[k_ph]) ++k_ph;
+    const int64_t bl = k_ph > 0 ? b - L.wg_end[k_ph - 1] : b;
+    const int64_t tpw = L.tpw[k_ph], ntasks = L.ntasks[k_ph];
+    const int64_t t0 = bl * tpw;
+    const int R = (int)(t0 + tpw < ntasks ? tpw : ntasks - t0);
+    const int64_t T0 = L.task_base[k_ph] + t0;
+    int64_t cA = -1, cB = -1;
+    if (tid < R) {
+        const TaskCells tc = task_cells(P, T0 + tid);
+        cA = tc.A;
+        cB = tc.slot == 0 ? -1 : tc.B;
+    }
+    bool waited = false;
+    auto wait = [&] {
+        if (waited) return;
+        waited = true;
+        if (g > 0) {   // each wave polls the cells of its lanes' tasks
+            bool ready = tid >= R;
+            const uint64_t t_wait = wall_clock64();
+            for (;;) {
+                if (!ready) {
+                    const uint32_t ea = __hip_atomic_load(epoch + cA, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t eb =
+                        cB < 0 ? (uint32_t)g
+                               : __hip_atomic_load(epoch + cB, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    ready = ea >= (uint32_t)g && eb >= (uint32_t)g;
+                }
+                if (__ballot(!ready) == 0ull) break;
+                if (wall_clock64() - t_wait > kWaitTicks) {
+                    if ((tid & 63) == 0) atomicOr(A.err, ERR_STALL);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        // every wave has seen its cells released; no state access of the
+        // range moves above the wait (the state loads are themselves
+        // coherent, so no cache invalidation is needed)
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    };
+    fd_range<K, true>(P, L, b, lds, A, cnt, negeps, wait);
+    // a range without pairs still orders its cells behind the predecessors
+    wait();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's state stores have completed
+    __syncthreads();                 // ... and those of the other waves
+    if (tid < R) {
+        __hip_atomic_store(epoch + cA, (uint32_t)g + 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        if (cB >= 0)
+            __hip_atomic_store(epoch + cB, (uint32_t)g + 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 template <int K>
 __global__ __launch_bounds__(FD_THREADS) void k_fd_sweep(const DevParams *__restrict__ Pp,
                                                  const FdSweep *__restrict__ SW,
@@ -536,68 +604,60 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_sweep(const DevParams *__rest
         if (it >= nitems) break;
         int g = 0;
         while (it >= SW->group_end[g]) ++g;
-        const FdLaunch &L = SW->launch[g];
-        const int64_t b = order[it];   // range index within group g
-        // the range's tasks (as fd_range finds them)
-        int k_ph = 0;
-        while (k_ph + 1 < L.nph && b >= L.wg_end[k_ph]) ++k_ph;
-        const int64_t bl = k_ph > 0 ? b - L.wg_end[k_ph - 1] : b;
-        const int64_t tpw = L.tpw[k_ph], ntasks = L.ntasks[k_ph];
-        const int64_t t0 = bl * tpw;
-        const int R = (int)(t0 + tpw < ntasks ? tpw : ntasks - t0);
-        const int64_t T0 = L.task_base[k_ph] + t0;
-        int64_t cA = -1, cB = -1;
-        if (tid < R) {
-            const TaskCells tc = task_cells(P, T0 + tid);
-            cA = tc.A;
-            cB = tc.slot == 0 ? -1 : tc.B;
-        }
-        bool waited = false;
-        auto wait = [&] {
-            if (waited) return;
-            waited = true;
-            if (g > 0) {   // each wave polls the cells of its lanes' tasks
-                bool ready = tid >= R;
-                const uint64_t t_wait = wall_clock64();
-                for (;;) {
-                    if (!ready) {
-                        const uint32_t ea = __hip_atomic_load(epoch + cA, __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT);
-                        const uint32_t eb =
-                            cB < 0 ? (uint32_t)g
-                                   : __hip_atomic_load(epoch + cB, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                        ready = ea >= (uint32_t)g && eb >= (uint32_t)g;
-                    }
-                    if (__ballot(!ready) == 0ull) break;
-                    if (wall_clock64() - t_wait > kWaitTicks) {
-                        if ((tid & 63) == 0) atomicOr(A.err, ERR_STALL);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-            }
-            // every wave has seen its cells released; no state access of the
-            // range moves above the wait (the state loads are themselves
-            // coherent, so no cache invalidation is needed)
-            __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        };
-        fd_range<K, true>(P, L, b, lds, A, cnt, negeps, wait);
-        // a range without pairs still orders its cells behind the predecessors
-        wait();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_s_waitcnt(0);   // this wave's state stores have completed
-        __syncthreads();                 // ... and those of the other waves
-        if (tid < R) {
-            __hip_atomic_store(epoch + cA, (uint32_t)g + 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            if (cB >= 0)
-                __hip_atomic_store(epoch + cB, (uint32_t)g + 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
+        // range index within group g
+        fd_flow_range<K>(P, SW->launch[g], g, order[it], A, epoch, lds, cnt, negeps);
     }
     fd_flush_counters(cnt, negeps, counters, A.err);
+}
+
+// The one-launch sweep of many boxes (batched replicas, fused layout): the
+// ranges of every box, group by group (all boxes' ranges of group 0, then of
+// group 1, ...; a box's ranges of one group in its own order), handed out by
+// one counter.  A range waits only on ranges of the previous group of its own
+// box, all handed out before it, so the argument of the one-box sweep holds.
+// While one box waits on its chain of groups the other boxes' ranges run.
+struct FdBoxDesc {
+    const DevParams *Pp;
+    const FdSweep *SW;
+    const uint32_t *order;
+    FdArgs A;
+    uint32_t *epoch;
+    unsigned long long *counters;
+};
+
+// item_off[g * (nbox + 1) + b]: the first item of box b in group g; entry
+// nbox of a row is the first item of the next group (nitems for the last)
+template <int K>
+__global__ __launch_bounds__(FD_THREADS) void k_fd_sweep_boxes(const FdBoxDesc *__restrict__ boxes,
+                                                       const uint32_t *__restrict__ item_off,
+                                                       int nbox, int ngroups, uint32_t nitems,
+                                                       uint32_t *work)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ uint32_t s_item;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(work, 1u);
+        __syncthreads();
+        const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_item);
+        if (it >= nitems) break;
+        int g = 0;
+        while (g + 1 < ngroups && it >= item_off[(int64_t)(g + 1) * (nbox + 1)]) ++g;
+        const uint32_t *row = item_off + (int64_t)g * (nbox + 1);
+        int lo = 0, hi = nbox;   // row[lo] <= it < row[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (it >= row[mid]) lo = mid;
+            else hi = mid;
+        }
+        const FdBoxDesc &D = boxes[lo];
+        const uint32_t gbeg = g > 0 ? D.SW->group_end[g - 1] : 0u;
+        FdCount cnt = {0u, 0u, 0u, 0u, 0u};
+        bool negeps = false;
+        fd_flow_range<K>(*D.Pp, D.SW->launch[g], g, D.order[gbeg + (it - row[lo])], D.A, D.epoch,
+                         lds, cnt, negeps);
+        fd_flush_counters(cnt, negeps, D.counters, D.A.err);
+    }
 }
 
 // ---------------------------------------------------------------- host side
@@ -631,8 +691,8 @@ PhaseGeom phase_geom(int phase)
 // and pair entries per task, and their spread (standard deviation per task),
 // measured on jittered lattices; then a headroom factor on both capacities.
 // The own-cell phase gains from room for the heavy ranges (lattice cells of
-// 27 particles) while it stays under 20 KB per wave, the LDS share of a
-// wave at two waves per SIMD.
+// 27 particles) while it stays under the LDS share of a workgroup at two
+// waves per SIMD (20 KB on a 160 KB CU).
 struct Allow {
     double mp, sp, me, se, room;
 };
@@ -654,7 +714,10 @@ int round_up(double x, int q)
 void fd_class_caps(const sdpd_ctx *c, int k, int t, int &cp, int &ce)
 {
     const double s = c->ncell > 0 ? ((double)c->n / (double)c->ncell) / 17.5 : 1.0;
-    const int lim = std::min(c->max_lds, 65536);
+    // within the LDS share of two waves per SIMD: boxes with dense cells
+    // (small boxes have up to ~34 particles per cell) would otherwise take
+    // tens of KB per workgroup and leave the CU a few workgroups
+    const int lim = std::min(std::min(c->max_lds, 65536), c->lds_share);
     const double st = std::sqrt((double)t);
     const double room = kAllow[k].room;
     cp = round_up((t * kAllow[k].mp + 4.0 * st * kAllow[k].sp) * s * room, 16);
@@ -928,6 +991,8 @@ int fd_prepare_sweep(sdpd_ctx *c)
     }
     h.nitems = (uint32_t)total;
     if (lds > (size_t)c->max_lds) return SDPD_EINVAL;
+    c->sweep_ngroups = h.ngroups;
+    memcpy(c->sweep_group_end, h.group_end, sizeof h.group_end);
     if (!c->sweep && hipMalloc(&c->sweep, sizeof(FdSweep)) != hipSuccess) {
         c->sweep = nullptr;
         return SDPD_ENOMEM;
@@ -1013,6 +1078,28 @@ int fd_launch_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
 {
     if (!c->sweep_ok) return SDPD_EINVAL;
     int rc;
+    if (c->rec && c->fd_record_flow) {
+        // fused batch: the epochs start at zero, then the sweep is recorded
+        // as this box's part of one multi-box launch
+        if ((rc = launch_fill_u32(c, c->epoch, 0u, c->ncell))) return rc;
+        FdBoxDesc d;
+        d.Pp = c->dparams;
+        d.SW = (const FdSweep *)c->sweep;
+        d.order = c->sweep_order;
+        d.A = fd_args(c, s, dt_fd);
+        d.epoch = c->epoch;
+        d.counters = c->counters;
+        RecordedLaunch r;
+        r.multi = nullptr;
+        r.grid = 1;
+        r.block = FD_THREADS;
+        r.lds = c->sweep_lds;
+        r.flow_kind = fd_kind(c);
+        r.args.resize(sizeof d);
+        memcpy(r.args.data(), &d, sizeof d);
+        c->rec->push_back(std::move(r));
+        return SDPD_OK;
+    }
     if (!fd_one_launch(c)) {
         for (const std::vector<int> &g : fd_groups())
             if ((rc = launch_phases(c, s, g.data(), (int)g.size(), dt_fd))) return rc;
@@ -1028,6 +1115,98 @@ int fd_launch_sweep(sdpd_ctx *c, const sdpd_state *s, double dt_fd)
                        c->epoch + c->ncell, c->epoch, c->counters);
     timer_end(c, TK_FD);
     return check_hip(hipGetLastError());
+}
+
+int fd_flow_build(const std::vector<sdpd_ctx *> &ctxs,
+                  const std::vector<const RecordedLaunch *> &recs, FlowSweep &out)
+{
+    const int nbox = (int)ctxs.size();
+    if (nbox < 1 || recs.size() != ctxs.size()) return SDPD_EINVAL;
+    out.kind = recs[0]->flow_kind;
+    out.nbox = nbox;
+    out.ngroups = ctxs[0]->sweep_ngroups;
+    std::vector<FdBoxDesc> desc(nbox);
+    out.lds = 0;
+    for (int b = 0; b < nbox; ++b) {
+        if (recs[b]->flow_kind != out.kind || ctxs[b]->sweep_ngroups != out.ngroups ||
+            recs[b]->args.size() != sizeof(FdBoxDesc))
+            return SDPD_EINVAL;
+        memcpy(&desc[b], recs[b]->args.data(), sizeof(FdBoxDesc));
+        out.lds = std::max(out.lds, recs[b]->lds);
+    }
+    // group-major item numbering: all boxes' ranges of group 0, then group 1, ...
+    std::vector<uint32_t> off((size_t)out.ngroups * (nbox + 1));
+    uint64_t item = 0;
+    for (int g = 0; g < out.ngroups; ++g)
+        for (int b = 0; b <= nbox; ++b) {
+            off[(size_t)g * (nbox + 1) + b] = (uint32_t)item;
+            if (b < nbox) {
+                const uint32_t *ge = ctxs[b]->sweep_group_end;
+                item += ge[g] - (g > 0 ? ge[g - 1] : 0u);
+                if (item > 0x7fffffffull) return SDPD_EINVAL;
+            }
+        }
+    out.nitems = (uint32_t)item;
+    int per_cu = 0, cus = 0;
+    const void *kern = out.kind == 2 ? (const void *)k_fd_sweep_boxes<2>
+                       : out.kind == 1 ? (const void *)k_fd_sweep_boxes<1>
+                                       : (const void *)k_fd_sweep_boxes<0>;
+    if (out.lds > 65536 &&
+        hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)out.lds) !=
+            hipSuccess)
+        return SDPD_EINVAL;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, FD_THREADS, out.lds) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctxs[0]->device) !=
+            hipSuccess || per_cu < 1 || cus < 1) {
+        (void)hipGetLastError();
+        return SDPD_EHIP;
+    }
+    out.grid = (unsigned)std::min<int64_t>((int64_t)per_cu * cus, std::max<int64_t>(item, 1));
+    if (hipMalloc(&out.boxes, sizeof(FdBoxDesc) * nbox) != hipSuccess ||
+        hipMalloc((void **)&out.item_off, sizeof(uint32_t) * off.size()) != hipSuccess ||
+        hipMalloc((void **)&out.work, sizeof(uint32_t)) != hipSuccess)
+        return SDPD_ENOMEM;
+    int rc = check_hip(hipMemcpy(out.boxes, desc.data(), sizeof(FdBoxDesc) * nbox,
+                                 hipMemcpyHostToDevice));
+    if (!rc)
+        rc = check_hip(hipMemcpy(out.item_off, off.data(), sizeof(uint32_t) * off.size(),
+                                 hipMemcpyHostToDevice));
+    return rc;
+}
+
+// counter of the multi-box sweep back to zero (a kernel, so that a captured
+// graph holds no memset node)
+__global__ void k_flow_reset(uint32_t *work)
+{
+    if (threadIdx.x == 0) *work = 0u;
+}
+
+int fd_flow_launch(const FlowSweep &f, hipStream_t stream)
+{
+    if (f.nitems == 0) return SDPD_OK;
+    hipLaunchKernelGGL(k_flow_reset, dim3(1), dim3(64), 0, stream, f.work);
+    const FdBoxDesc *boxes = (const FdBoxDesc *)f.boxes;
+    if (f.kind == 2)
+        hipLaunchKernelGGL(k_fd_sweep_boxes<2>, dim3(f.grid), dim3(FD_THREADS), f.lds, stream,
+                           boxes, f.item_off, f.nbox, f.ngroups, f.nitems, f.work);
+    else if (f.kind == 1)
+        hipLaunchKernelGGL(k_fd_sweep_boxes<1>, dim3(f.grid), dim3(FD_THREADS), f.lds, stream,
+                           boxes, f.item_off, f.nbox, f.ngroups, f.nitems, f.work);
+    else
+        hipLaunchKernelGGL(k_fd_sweep_boxes<0>, dim3(f.grid), dim3(FD_THREADS), f.lds, stream,
+                           boxes, f.item_off, f.nbox, f.ngroups, f.nitems, f.work);
+    return check_hip(hipGetLastError());
+}
+
+void fd_flow_free(FlowSweep &f)
+{
+    if (f.boxes) (void)hipFree(f.boxes);
+    if (f.item_off) (void)hipFree(f.item_off);
+    if (f.work) (void)hipFree(f.work);
+    f.boxes = nullptr;
+    f.item_off = nullptr;
+    f.work = nullptr;
 }
 
 // The step index of the draws is read from c->dstep on the device (set by

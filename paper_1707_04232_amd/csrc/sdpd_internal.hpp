@@ -98,6 +98,7 @@ using MultiKernel = void (*)(const void *, const uint2 *);
 struct RecordedLaunch {
     MultiKernel multi;
     unsigned grid, block;
+    int flow_kind = -1;   // >= 0: a one-launch F/D sweep (args: the box's descriptor)
     size_t lds;
     std::vector<unsigned char> args;
 };
@@ -143,6 +144,7 @@ struct sdpd_ctx {
     int fd_swept;                // a schedule has been built (sdpd_fd_schedule_size)
     sdpd_tuning tuning;          // F/D workgroup sizes and LDS capacities per phase class
     int max_lds;                 // LDS bytes one workgroup may use
+    int lds_share;               // LDS bytes of one sweep workgroup at two waves per SIMD
     // pair schedule (rebuilt before every sweep)
     uint32_t *task_count, *task_np, *pair_off, *part_off, *part_list;
     uint64_t *pairs;
@@ -152,6 +154,9 @@ struct sdpd_ctx {
     int tune_gen = 0;            // counts sdpd_tune calls (captured batches check it)
     int fd_dataflow = 0;         // SDPD_SWEEP_AUTO chooses one launch (large boxes)
     int fd_per_group = 0;        // force one launch per group (set while a batch captures)
+    int fd_record_flow = 0;      // recording: the sweep as one multi-box launch (fused batch)
+    int sweep_ngroups = 0;       // host copy of the sweep table's group ends
+    uint32_t sweep_group_end[32] = {};
     int sweep_mode = 0;          // SDPD_SWEEP_*
     size_t sweep_lds = 0;
     int sweep_grid = 0, sweep_ok = 0;
@@ -198,6 +203,21 @@ void fd_class_caps(const sdpd_ctx *c, int k, int t, int &cp, int &ce);
 int fd_check_tuning(const sdpd_ctx *c, const sdpd_tuning *t);
 int fd_prepare_sweep(sdpd_ctx *c);   // after any change of the tuning
 bool fd_one_launch(const sdpd_ctx *c);   // the sweep runs as one launch
+// The one-launch sweep of many boxes (fused batch): built from the boxes'
+// flow records of one position, launched (with its counter reset) on a stream.
+struct FlowSweep {
+    int kind = 0, nbox = 0, ngroups = 0;
+    uint32_t nitems = 0;
+    size_t lds = 0;
+    unsigned grid = 0;
+    void *boxes = nullptr;          // device: the boxes' descriptors
+    uint32_t *item_off = nullptr;   // device: ngroups x (nbox + 1) first items
+    uint32_t *work = nullptr;       // device: the range counter
+};
+int fd_flow_build(const std::vector<sdpd_ctx *> &ctxs,
+                  const std::vector<const RecordedLaunch *> &recs, FlowSweep &out);
+int fd_flow_launch(const FlowSweep &f, hipStream_t stream);
+void fd_flow_free(FlowSweep &f);
 int run_observe(sdpd_ctx *c, const sdpd_state *s, double *dst_record);
 // observables of n = dp.n particles into dst_record (REC doubles, or the
 // first 7 when counters is NULL); partial holds 6 doubles per block of

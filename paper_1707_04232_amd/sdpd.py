@@ -18,7 +18,7 @@ KERNEL_LUCY, KERNEL_CUBIC = 0, 1
 FD_EMS, FD_AMS, FD_SSA, FD_NONE = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 SWEEP_AUTO, SWEEP_ONE, SWEEP_PER_GROUP = 0, 1, 2
-BATCH_AUTO, BATCH_FUSED, BATCH_GRAPHS = 0, 1, 2
+BATCH_AUTO, BATCH_FUSED, BATCH_GRAPHS, BATCH_FUSED_FLOW = 0, 1, 2, 3
 TIMING_CLASSES = ("cells", "density", "fd", "forces", "observe", "schedule")
 
 EXPORTS = ("sdpd_create", "sdpd_destroy", "sdpd_build_cells", "sdpd_cell_info",
@@ -407,8 +407,9 @@ class Context:
 
 class Batch:
     """Many boxes (contexts with their states) advanced together: by default
-    every stage of a step is one launch for all boxes (BATCH_FUSED); with
-    BATCH_GRAPHS each box's own launches are captured."""
+    every stage of a step is one launch for all boxes (BATCH_FUSED; with
+    BATCH_FUSED_FLOW the F/D sweeps of all boxes are one persistent launch);
+    with BATCH_GRAPHS each box's own launches are captured."""
 
     def __init__(self, contexts, states, layout=BATCH_AUTO, parts=0):
         self._ctx = list(contexts)
@@ -421,7 +422,7 @@ class Batch:
                                               C.byref(self._h)), "sdpd_batch_create_layout")
 
     def layout(self) -> int:
-        """The layout in use (BATCH_FUSED or BATCH_GRAPHS)."""
+        """The layout in use (BATCH_FUSED, BATCH_FUSED_FLOW or BATCH_GRAPHS)."""
         m = lib().sdpd_batch_layout(self._h)
         if m < 0:
             _check(m, "sdpd_batch_layout")

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_messages():
     L = sdpd.lib()
-    assert L.sdpd_abi_version() == 7
+    assert L.sdpd_abi_version() == 8
     for rc in (0, -1, -2, -3, -4, -5, -6):
         assert L.sdpd_strerror(rc)
     assert L.sdpd_strerror(-99) == b"unknown status"

@@ -39,7 +39,10 @@ def _boxes(nbox, fd_every, streams):
     return out
 
 
-@pytest.mark.parametrize("layout", ["fused", "graphs"])
+LAYOUTS = {"fused": 1, "flow": 3, "graphs": 2}   # sdpd.BATCH_*
+
+
+@pytest.mark.parametrize("layout", list(LAYOUTS))
 @pytest.mark.parametrize("fd_every", [1, 2])
 def test_batch_graph_matches_eager_steps(fd_every, layout):
     import torch
@@ -49,7 +52,7 @@ def test_batch_graph_matches_eager_steps(fd_every, layout):
     ref = _boxes(6, fd_every, None)
     bat = _boxes(6, fd_every, streams)
     torch.cuda.synchronize()
-    want = sdpd.BATCH_FUSED if layout == "fused" else sdpd.BATCH_GRAPHS
+    want = LAYOUTS[layout]
     with sdpd.Batch([c for c, _ in bat], [s for _, s in bat], layout=want) as B:
         assert B.layout() == want
         with pytest.raises(sdpd.SdpdError):
@@ -123,7 +126,7 @@ def test_batch_per_stream_graphs_match_eager_steps():
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout[-2000:] + r.stderr[-2000:]
 
 
-@pytest.mark.parametrize("layout", ["fused", "graphs"])
+@pytest.mark.parametrize("layout", list(LAYOUTS))
 def test_batch_refuses_a_retuned_context(layout):
     import torch
     from paper_1707_04232_amd import sdpd
@@ -131,7 +134,7 @@ def test_batch_refuses_a_retuned_context(layout):
     streams = [torch.cuda.Stream() for _ in range(2)]
     bat = _boxes(2, 1, streams)
     torch.cuda.synchronize()
-    want = sdpd.BATCH_FUSED if layout == "fused" else sdpd.BATCH_GRAPHS
+    want = LAYOUTS[layout]
     with sdpd.Batch([c for c, _ in bat], [s for _, s in bat], layout=want) as B:
         B.run(0, 1)
         t = bat[0][0].get_tuning()
@@ -187,7 +190,8 @@ def _batch_of(init, streams):
     return out
 
 
-def test_batch_boxes_match_oracle():
+@pytest.mark.parametrize("layout", ["fused", "flow"])
+def test_batch_boxes_match_oracle(layout):
     """Each box of a captured batch (replica 0, 3, 255; a 64-bit key) after
     four replayed steps against the oracle at 1e-10.  The GPU's marginal
     decisions are a subset of the oracle pairs inside the widened window of
@@ -197,14 +201,15 @@ def test_batch_boxes_match_oracle():
     import torch
     from paper_1707_04232_amd import sdpd
     nsteps = 4
-    say("batch boxes vs oracle", ORACLE_BOXES)
+    say("batch boxes vs oracle", ORACLE_BOXES, "layout", layout)
     init, fin, logs = _oracle_boxes(nsteps)
     nseed = sum(int(PU.seeds(lg, O.FD_EMS, float(np.abs(eb).max())).sum())
                 for box in logs for (_, lg, eb) in box)
     say(f"oracle pairs inside the marginal window: {nseed}")
     streams = [torch.cuda.Stream() for _ in range(3)]
     bat = _batch_of(init, streams)
-    with sdpd.Batch([c for c, _ in bat], [s for _, s in bat]) as B:
+    with sdpd.Batch([c for c, _ in bat], [s for _, s in bat], layout=LAYOUTS[layout]) as B:
+        assert B.layout() == LAYOUTS[layout]
         if nseed == 0:
             B.run(0, nsteps)
             for (c, S), R, lg in zip(bat, fin, logs):
@@ -241,14 +246,16 @@ def test_batch_boxes_match_oracle():
         c.close()
 
 
-def test_fused_batch_mixed_precision_and_schemes_match_eager():
+@pytest.mark.parametrize("layout", ["fused", "flow"])
+def test_fused_batch_mixed_precision_and_schemes_match_eager(layout):
     """Boxes of different precision (FP64 and the FP32 density/force form),
     schemes (EMS, AMS), kernels and sizes (one above the four-lane density
     limit of 2^17 particles) in one fused batch: every box bit-identical to
-    its eager steps."""
+    its eager steps.  In the flow layout the boxes' sweeps fall into three
+    one-launch sweeps (FP64, the FP32 proposal, the general kernel)."""
     import torch
     from paper_1707_04232_amd import sdpd
-    say("fused batch: mixed precisions and schemes")
+    say("fused batch: mixed precisions and schemes, layout", layout)
     specs = [dict(side=10, prec=sdpd.MIXED), dict(side=12, fd=sdpd.FD_AMS),
              dict(side=11, kernel=sdpd.KERNEL_CUBIC, zeta=0.3),
              dict(side=52, prec=sdpd.FP64), dict(side=13, prec=sdpd.MIXED, fd=sdpd.FD_AMS)]
@@ -272,8 +279,8 @@ def test_fused_batch_mixed_precision_and_schemes_match_eager():
     ref = make(None)
     bat = make(streams)
     torch.cuda.synchronize()
-    with sdpd.Batch([c for c, _ in bat], [s for _, s in bat]) as B:
-        assert B.layout() == sdpd.BATCH_FUSED
+    with sdpd.Batch([c for c, _ in bat], [s for _, s in bat], layout=LAYOUTS[layout]) as B:
+        assert B.layout() == LAYOUTS[layout]
         for rep in range(2):
             B.run(3 * rep, 3)
             for c, S in ref:
