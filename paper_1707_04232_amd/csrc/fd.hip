@@ -148,7 +148,7 @@ struct FdArgs {
 // everything before it (entries, lists, ids, positions, the draws) is fixed
 // during the sweep, so the level sort and the draws of a range overlap the
 // wait for its predecessors.
-template <int K, bool COHERENT, class Wait>
+template <int K, bool COHERENT, bool VREG, class Wait>
 __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, int64_t b,
                                          unsigned char *lds, const FdArgs &A, FdCount &cnt,
                                          bool &negeps, Wait &wait)
@@ -405,6 +405,26 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
                 }
                 return v;
             };
+            // the constants the pair update reads are held in vector registers
+            // for the level loop where they fit (VREG: the one-box kernels of
+            // the common case); otherwise they stay scalar loads from P
+            PairRegs pr;
+            if (VREG) {
+                for (int a = 0; a < 3; ++a) {
+                    pr.box[a] = P.box[a];
+                    pr.half_box[a] = P.half_box[a];
+                    __asm__ volatile("" : "+v"(pr.box[a]), "+v"(pr.half_box[a]));
+                }
+                pr.inv_Cv = P.inv_Cv;
+                pr.kB = P.kB;
+                pr.two_over_Cv = P.two_over_Cv;
+                pr.inv_m = P.inv_m;
+                pr.b2_c = P.b2_c;
+                pr.kperp_c = P.kperp_c;
+                pr.cF = P.cF;
+                __asm__ volatile("" : "+v"(pr.inv_Cv), "+v"(pr.kB), "+v"(pr.two_over_Cv),
+                                 "+v"(pr.inv_m), "+v"(pr.b2_c), "+v"(pr.kperp_c), "+v"(pr.cF));
+            }
             int l0 = lo, b0 = (int)s_off[lo] - FD_THREADS;
             advance(l0, b0);
             int l1 = l0, b1 = b0;
@@ -419,7 +439,12 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
                 PairGeo g2 = {};
                 int li2 = 0, lj2 = 0;
                 const bool v2 = fetch(l2, b2, li2, lj2, g2);
-                if (v0) fd_pair<K != 0, K == 2>(P, dt, li0, lj0, g0, s_p, CP, s_eps, cnt, negeps);
+                if (v0) {
+                    if (VREG)
+                        fd_pair<K != 0, K == 2>(P, pr, dt, li0, lj0, g0, s_p, CP, s_eps, cnt, negeps);
+                    else
+                        fd_pair<K != 0, K == 2>(P, P, dt, li0, lj0, g0, s_p, CP, s_eps, cnt, negeps);
+                }
                 __syncthreads();
                 g0 = g1;
                 li0 = li1;
@@ -481,7 +506,7 @@ __device__ __forceinline__ void fd_phase_body(const FdPhaseArgs &a, uint32_t blk
     FdCount cnt = {0u, 0u, 0u, 0u, 0u};
     bool negeps = false;
     auto no_wait = [] {};
-    fd_range<K, false>(*a.Pp, a.L, (int64_t)blk, lds, a.A, cnt, negeps, no_wait);
+    fd_range<K, false, K != 0>(*a.Pp, a.L, (int64_t)blk, lds, a.A, cnt, negeps, no_wait);
     fd_flush_counters(cnt, negeps, a.counters, a.A.err);
 }
 template <int K>
@@ -517,7 +542,7 @@ constexpr uint64_t kWaitTicks = 20ull * 100000000ull;   // 20 s
 
 // One range of the one-launch sweep: range b of group g, waiting until the
 // cells of its tasks have epoch g and setting them to g + 1 afterwards.
-template <int K>
+template <int K, bool VREG>
 __device__ __forceinline__ void fd_flow_range(const DevParams &P, const FdLaunch &L, int g,
                                               int64_t b, const FdArgs &A, uint32_t *epoch,
                                               unsigned char *lds, FdCount &cnt, bool &negeps)
@@ -568,7 +593,7 @@ __device__ __forceinline__ void fd_flow_range(const DevParams &P, const FdLaunch
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     };
-    fd_range<K, true>(P, L, b, lds, A, cnt, negeps, wait);
+    fd_range<K, true, VREG>(P, L, b, lds, A, cnt, negeps, wait);
     // a range without pairs still orders its cells behind the predecessors
     wait();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -605,7 +630,7 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_sweep(const DevParams *__rest
         int g = 0;
         while (it >= SW->group_end[g]) ++g;
         // range index within group g
-        fd_flow_range<K>(P, SW->launch[g], g, order[it], A, epoch, lds, cnt, negeps);
+        fd_flow_range<K, K != 0>(P, SW->launch[g], g, order[it], A, epoch, lds, cnt, negeps);
     }
     fd_flush_counters(cnt, negeps, counters, A.err);
 }
@@ -650,11 +675,15 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_sweep_boxes(const FdBoxDesc *
             if (it >= row[mid]) lo = mid;
             else hi = mid;
         }
+        // box and group are the same in every lane: say so, so that the
+        // descriptor and the box's parameters are read as scalars
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        g = __builtin_amdgcn_readfirstlane(g);
         const FdBoxDesc &D = boxes[lo];
         const uint32_t gbeg = g > 0 ? D.SW->group_end[g - 1] : 0u;
         FdCount cnt = {0u, 0u, 0u, 0u, 0u};
         bool negeps = false;
-        fd_flow_range<K>(*D.Pp, D.SW->launch[g], g, D.order[gbeg + (it - row[lo])], D.A, D.epoch,
+        fd_flow_range<K, false>(*D.Pp, D.SW->launch[g], g, D.order[gbeg + (it - row[lo])], D.A, D.epoch,
                          lds, cnt, negeps);
         fd_flush_counters(cnt, negeps, D.counters, D.A.err);
     }

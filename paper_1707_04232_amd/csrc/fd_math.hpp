@@ -71,20 +71,20 @@ struct Coef {
 // When zeta = 0 the parallel friction is exactly twice the perpendicular one,
 // and expm1(2y) = e (2 + e) with e = expm1(y) saves one exponential.
 // FAST = the common case fixed at compile time: EMS, Lucy kernel, zeta = 0
-template <bool FAST>
-__device__ __forceinline__ Coef fd_coef(const DevParams &P, double kpar, double kperp, double ei,
-                                        double ej, double dt)
+template <bool FAST, class R>
+__device__ __forceinline__ Coef fd_coef(const DevParams &P, const R &pr, double kpar, double kperp,
+                                        double ei, double ej, double dt)
 {
 #pragma clang fp contract(fast)
-    const double Ti = ei * P.inv_Cv, Tj = ej * P.inv_Cv;
+    const double Ti = ei * pr.inv_Cv, Tj = ej * pr.inv_Cv;
     const double inv_Ts = fast_rcp(Ti + Tj);
     const double Tred = Ti * Tj * inv_Ts;
-    const double d = P.kB * Tred * inv_Ts * P.two_over_Cv;
+    const double d = pr.kB * Tred * inv_Ts * pr.two_over_Cv;
     const double omd = 1.0 - d;
-    const double c = -2.0 * dt * P.inv_m * omd;
+    const double c = -2.0 * dt * pr.inv_m * omd;
     const double e_perp = fd_expm1(c * kperp);
     const double e_par = (FAST || P.par_twice_perp) ? e_perp * (2.0 + e_perp) : fd_expm1(c * kpar);
-    const double s = P.b2_c * Tred * fast_rcp(omd);
+    const double s = pr.b2_c * Tred * fast_rcp(omd);
     Coef r;
     r.al_par = 1.0 + e_par;
     r.al_perp = 1.0 + e_perp;
@@ -181,20 +181,30 @@ __device__ __forceinline__ double log1p_cubic(double x)
 // rounding of both evaluations (below 1e-13 for the values that occur).
 constexpr double kLazyMargin = 2e-9;
 
+// The parameters the pair update reads in its dependent chain (the box for
+// the minimum image, the constants of the coefficients), by the names of
+// DevParams: the update takes either DevParams itself or this copy, which
+// the level loop holds in vector registers (read once per batch), so that
+// no scalar load waits inside the loop.
+struct PairRegs {
+    double box[3], half_box[3];
+    double inv_Cv, kB, two_over_Cv, inv_m, b2_c, kperp_c, cF;
+};
+
 // One pair update; li has the smaller id.  Momenta (x, y, z planes at
 // stride ps) and energies are LDS-resident.  MIX (with FAST only): the
 // geometry and the proposal coefficients in FP32 (fd_coef_f32).
-template <bool FAST, bool MIX = false>
-__device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
+template <bool FAST, bool MIX = false, class R = DevParams>
+__device__ __forceinline__ void fd_pair(const DevParams &P, const R &bx, double dt, int li,
                                         int lj, const PairGeo &pg, double *s_p, int ps,
                                         double *s_eps, FdCount &cnt, bool &negeps)
 {
 #pragma clang fp contract(fast)
     static_assert(!MIX || FAST, "the FP32 proposal covers EMS, Lucy's kernel, zeta = 0");
     // geometry (Sec. 2.1.1): r_ij, e_ij, F_ij
-    const double dx = min_image(pg.xi - pg.xj, P.box[0], P.half_box[0]);
-    const double dy = min_image(pg.yi - pg.yj, P.box[1], P.half_box[1]);
-    const double dz = min_image(pg.zi - pg.zj, P.box[2], P.half_box[2]);
+    const double dx = min_image(pg.xi - pg.xj, bx.box[0], bx.half_box[0]);
+    const double dy = min_image(pg.yi - pg.yj, bx.box[1], bx.half_box[1]);
+    const double dz = min_image(pg.zi - pg.zj, bx.box[2], bx.half_box[2]);
     double ex, ey, ez, kpar = 0.0, kperp = 0.0;
     float kperp_f = 0.0f;
     if (MIX) {
@@ -217,12 +227,12 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
         ez = dz * inv_r;
         const double x = r * P.inv_h, t = 1.0 - x;
         double F;
-        if (FAST || P.kernel == SDPD_KERNEL_LUCY) F = P.cF * (t * t);
-        else F = x <= 0.5 ? P.cF * (2.0 - 3.0 * x) : P.cF * P.h * (t * t) * inv_r;
+        if (FAST || P.kernel == SDPD_KERNEL_LUCY) F = bx.cF * (t * t);
+        else F = x <= 0.5 ? bx.cF * (2.0 - 3.0 * x) : bx.cF * P.h * (t * t) * inv_r;
         // kappa^theta of Sec. 2.2.2
         const double kfac = F * fast_rcp(pg.rho_i * pg.rho_j);
         kpar = P.kpar_c * kfac;
-        kperp = P.kperp_c * kfac;
+        kperp = bx.kperp_c * kfac;
     }
 
     const double ei = s_eps[li], ej = s_eps[lj];
@@ -234,7 +244,7 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
 
     // proposal, eq. (proposal): v' = A(v) v + B(v) G, B = (2/m) zeta^theta P^theta
     const Coef f = MIX ? fd_coef_f32(P, kperp_f, ei, ej, (float)dt)
-                       : fd_coef<FAST>(P, kpar, kperp, ei, ej, dt);
+                       : fd_coef<FAST>(P, bx, kpar, kperp, ei, ej, dt);
     const double b_par = MIX ? f.b_par : fd_sqrt(f.b2_par);
     const double b_perp = MIX ? f.b_perp : fd_sqrt(f.b2_perp);
     const double vpar = vx * ex + vy * ey + vz * ez;
@@ -266,7 +276,7 @@ __device__ __forceinline__ void fd_pair(const DevParams &P, double dt, int li,
             // reverse move from v' at the proposed energies, eq. (metropolis-ratio)
             const double ei2 = ei - delta, ej2 = ej - delta;
             const Coef g = MIX ? fd_coef_f32(P, kperp_f, ei2, ej2, (float)dt)
-                               : fd_coef<FAST>(P, kpar, kperp, ei2, ej2, dt);
+                               : fd_coef<FAST>(P, bx, kpar, kperp, ei2, ej2, dt);
             const double wpar = vpar - g.al_par * npar;
             const double wqx = vqx - g.al_perp * nqx;
             const double wqy = vqy - g.al_perp * nqy;
