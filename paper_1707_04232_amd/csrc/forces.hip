@@ -58,54 +58,111 @@ struct ForcesArgs {
     double *f, *p;
     int half_kick;
 };
+
+// One loop over a lane's partners in that order: the trip count is the
+// lane's partner count, and a lane moves on to its next non-empty neighbour
+// cell inside the loop body, whose cell start and mask are loaded one cell
+// ahead.  A wave then runs as many iterations as its busiest lane has
+// partners, instead of the sum over the 27 cells of the busiest lane in
+// each.  EDGE: some lane of the wave sits in a first or last cell of an
+// axis, where neighbour steps wrap and carry a periodic shift; elsewhere
+// cell k is c + o_x + o_y n_x + o_z n_x n_y - (1 + n_x + n_x n_y) for the
+// offset digits o of k, with no shift.
+template <bool EDGE>
+__device__ __forceinline__ void forces_flat_loop(const DevParams &P, const double *__restrict__ q4,
+                                                 const uint32_t *__restrict__ cell_start,
+                                                 const uint64_t *__restrict__ masks, int64_t i,
+                                                 uint32_t c, const NbSteps &nb, uint32_t todo,
+                                                 int total, double4 qi, double &fx, double &fy,
+                                                 double &fz)
+{
+    const int64_t n = P.n;
+    const uint32_t nx = (uint32_t)P.nc[0], nxy = nx * (uint32_t)P.nc[1];
+    const uint32_t c0 = c - 1u - nx - nxy;
+    const double xi = qi.x, yi = qi.y, zi = qi.z, pii = qi.w;
+    const double m2 = P.m * P.m;
+    // cell k: start and mask requested, shift set
+    auto cell = [&](int k, uint32_t &start, uint64_t &m, double &hx, double &hy, double &hz) {
+        uint32_t cn;
+        if (EDGE) {
+            const NbCell r = nb.get(P, k);
+            cn = (uint32_t)r.c;
+            hx = r.sx;
+            hy = r.sy;
+            hz = r.sz;
+        } else {
+            const uint32_t q3 = ((uint32_t)k * 11u) >> 5;   // k / 3 for k < 27
+            const uint32_t o0 = (uint32_t)k - 3u * q3, o2 = (q3 * 11u) >> 5, o1 = q3 - 3u * o2;
+            cn = c0 + o0 + o1 * nx + o2 * nxy;
+        }
+        start = cell_start[cn];
+        m = masks[(int64_t)k * n + i];
+    };
+    uint64_t mask = 0ull, mn = 0ull;
+    uint32_t s = 0u, sn = 0u;
+    double sx = 0.0, sy = 0.0, sz = 0.0, shx = 0.0, shy = 0.0, shz = 0.0;
+    if (todo) {
+        cell(__builtin_ctz(todo), sn, mn, shx, shy, shz);
+        todo &= todo - 1u;
+    }
+    for (int t = 0; t < total; ++t) {
+        if (mask == 0ull) {   // the prefetched cell becomes current
+            s = sn;
+            mask = mn;
+            if (EDGE) {
+                sx = shx;
+                sy = shy;
+                sz = shz;
+            }
+            if (todo) {
+                cell(__builtin_ctz(todo), sn, mn, shx, shy, shz);
+                todo &= todo - 1u;
+            }
+        }
+        const uint32_t j = s + (uint32_t)__builtin_ctzll(mask);
+        mask &= mask - 1ull;
+        const double4 qj = reinterpret_cast<const double4 *>(q4)[j];
+        // without a shift x_i - x_j is never -0, so adding +0 changes no bit
+        const double dx = EDGE ? (xi - qj.x) + sx : xi - qj.x;
+        const double dy = EDGE ? (yi - qj.y) + sy : yi - qj.y;
+        const double dz = EDGE ? (zi - qj.z) + sz : zi - qj.z;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        // coincident particles (r = 0): F(sqrt(DBL_MIN)) = F(0) and dx = 0
+        const double sc = m2 * (pii + qj.w) * kernel_f(P, fd_sqrt(fmax(r2, DBL_MIN)));
+        fx += sc * dx;
+        fy += sc * dy;
+        fz += sc * dz;
+    }
+}
+
 __device__ __forceinline__ void forces_body(const ForcesArgs &a, uint32_t blk)
 {
     const DevParams &P = a.P;
-    const double *__restrict__ q4 = a.q4;
-    const uint32_t *__restrict__ cell_sorted = a.cell_sorted;
-    const uint32_t *__restrict__ cell_start = a.cell_start;
-    const uint64_t *__restrict__ masks = a.masks;
-    double *f = a.f, *p = a.p;
-    const int half_kick = a.half_kick;
     const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
     const int64_t n = P.n;
-    const uint32_t c = cell_sorted[i];
-    const int cx = (int)(c % (uint32_t)P.nc[0]);
-    const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
-    const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
-    const double4 qi = reinterpret_cast<const double4 *>(q4)[i];
-    const double xi = qi.x, yi = qi.y, zi = qi.z, pii = qi.w;
-    const double m2 = P.m * P.m;
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    // the mask of the next neighbour cell is in flight while this one's
-    // partners are summed
-    uint64_t next = masks[i];
+    const uint32_t c = a.cell_sorted[i];
+    const uint32_t nx = (uint32_t)P.nc[0], ny = (uint32_t)P.nc[1];
+    const NbSteps nb(P, (int)(c % nx), (int)((c / nx) % ny), (int)(c / (nx * ny)));
+    const double4 qi = reinterpret_cast<const double4 *>(a.q4)[i];
+    // non-empty neighbour cells (bit k) and the number of partners
+    uint32_t todo = 0u;
+    int total = 0;
     for (int k = 0; k < 27; ++k) {
-        uint64_t mask = next;
-        if (k + 1 < 27) next = masks[(int64_t)(k + 1) * n + i];
-        if (!mask) continue;
-        const NbCell nb = neighbour_cell(P, cx, cy, cz, k);
-        const uint32_t s = cell_start[nb.c];
-        while (mask) {
-            const uint32_t j = s + (uint32_t)__builtin_ctzll(mask);
-            mask &= mask - 1ull;
-            const double4 qj = reinterpret_cast<const double4 *>(q4)[j];
-            const double dx = (xi - qj.x) + nb.sx;
-            const double dy = (yi - qj.y) + nb.sy;
-            const double dz = (zi - qj.z) + nb.sz;
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            // coincident particles (r = 0): F(sqrt(DBL_MIN)) = F(0) and dx = 0
-            const double sc = m2 * (pii + qj.w) * kernel_f(P, fd_sqrt(fmax(r2, DBL_MIN)));
-            fx += sc * dx;
-            fy += sc * dy;
-            fz += sc * dz;
-        }
+        const uint64_t m = a.masks[(int64_t)k * n + i];
+        todo |= (m != 0ull ? 1u : 0u) << k;
+        total += __popcll(m);
     }
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (__ballot((nb.lo | nb.hi) != 0u))
+        forces_flat_loop<true>(P, a.q4, a.cell_start, a.masks, i, c, nb, todo, total, qi, fx, fy, fz);
+    else
+        forces_flat_loop<false>(P, a.q4, a.cell_start, a.masks, i, c, nb, todo, total, qi, fx, fy, fz);
+    double *f = a.f, *p = a.p;
     f[i] = fx;
     f[n + i] = fy;
     f[2 * n + i] = fz;
-    if (half_kick) {
+    if (a.half_kick) {
         const double hd = 0.5 * P.dt;
         p[i] += hd * fx;
         p[n + i] += hd * fy;
