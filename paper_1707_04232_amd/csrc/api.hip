@@ -168,7 +168,7 @@ static void free_ctx(sdpd_ctx *c)
                     c->perm, c->cell_sorted, c->tq, c->tp, c->teps, c->trho, c->tf, c->tid,
                     c->masks, c->counters, c->err, c->obs_partial, c->obs_out,
                     c->dparams, c->task_count, c->task_np, c->pair_off, c->part_off,
-                    c->part_list, c->pairs, c->draws, c->qr, c->pi_f, c->dstep, c->q4,
+                    c->part_list, c->pairs, c->draws, c->q4f, c->dstep, c->q4,
                     c->sweep, c->epoch, c->sweep_order};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -312,10 +312,7 @@ int sdpd_create(const sdpd_params *params, void *hip_stream, sdpd_ctx **out)
     rc = rc ? rc : dalloc(&c->trho, n);
     rc = rc ? rc : dalloc(&c->tid, n);
     rc = rc ? rc : dalloc(&c->q4, 4 * n);
-    if (c->dp.mixed) {
-        rc = rc ? rc : dalloc(&c->qr, 3 * n);
-        rc = rc ? rc : dalloc(&c->pi_f, n);
-    }
+    if (c->dp.mixed) rc = rc ? rc : dalloc(&c->q4f, 4 * n);
     rc = rc ? rc : dalloc(&c->masks, (size_t)NNB * n);
     rc = rc ? rc : dalloc(&c->counters, (size_t)CNT_N);
     rc = rc ? rc : dalloc(&c->err, 1);

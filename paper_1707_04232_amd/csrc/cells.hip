@@ -278,8 +278,9 @@ __device__ __forceinline__ void rank_body(const RankArgs &a, uint32_t blk)
 __global__ void k_rank(RankArgs a) { rank_body(a, blockIdx.x); }
 SDPD_MULTI_KERNEL(k_rank_multi, RankArgs, rank_body, 256)
 
-// gather into (cell, id) order; with qr (mixed precision) also the FP32
-// position relative to the particle's cell origin
+// gather into (cell, id) order; with q4f (mixed precision) also the FP32
+// position relative to the particle's cell origin, in the x, y, z slots of
+// the particle's 16-byte record (the w slot takes P/rho^2 later)
 struct GatherArgs {
     DevParams P;
     int64_t n;
@@ -288,7 +289,7 @@ struct GatherArgs {
     const uint32_t *id;
     double *tq, *tp, *teps, *trho, *tf;
     uint32_t *tid, *cell_sorted;
-    float *qr;
+    float *q4f;
     double *q4;
 };
 __device__ __forceinline__ void gather_body(const GatherArgs &a, uint32_t blk)
@@ -300,18 +301,18 @@ __device__ __forceinline__ void gather_body(const GatherArgs &a, uint32_t blk)
     const uint32_t *id = a.id;
     double *tq = a.tq, *tp = a.tp, *teps = a.teps, *trho = a.trho, *tf = a.tf;
     uint32_t *tid = a.tid, *cell_sorted = a.cell_sorted;
-    float *qr = a.qr;
+    float *q4f = a.q4f;
     double *q4 = a.q4;
     int64_t k = (int64_t)blk * blockDim.x + threadIdx.x;
     if (k >= n) return;
     uint32_t i = perm[k];
-    if (qr) {
+    if (q4f) {
         const uint32_t c = cell_of[i];
         const int cc[3] = {(int)(c % (uint32_t)P.nc[0]), (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]),
                            (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]))};
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-            qr[d * n + k] = (float)(q[d * n + i] - (double)cc[d] * (P.box[d] / P.nc[d]));
+            q4f[4 * k + d] = (float)(q[d * n + i] - (double)cc[d] * (P.box[d] / P.nc[d]));
     }
     q4[4 * k] = q[i];
     q4[4 * k + 1] = q[n + i];
@@ -423,7 +424,7 @@ int run_build_cells(sdpd_ctx *c, const sdpd_state *s, int kick_drift)
             rc = launch_or_record(c, k_gather, k_gather_multi, g, 256, 0,
                                   GatherArgs{c->dp, n, c->perm, c->cell_of, s->q, s->p, s->eps,
                                              s->rho, s->f, s->id, c->tq, c->tp, c->teps, c->trho,
-                                             tf, c->tid, c->cell_sorted, c->qr, c->q4});
+                                             tf, c->tid, c->cell_sorted, c->q4f, c->q4});
         if (!rc)
             rc = launch_or_record(c, k_copy_back, k_copy_back_multi, g, 256, 0,
                                   CopyBackArgs{n, c->tq, c->tp, tf, c->teps, c->trho, c->tid, s->q,

@@ -51,7 +51,7 @@ __device__ __forceinline__ NbCellF neighbour_cell_f32(const DevParams &P, int cx
 // masks[k * n + i] as in the FP64 pass (bit = slot of an active partner).
 struct DensityF32Args {
     DevParams P;
-    const float *qr;
+    const float *q4f;
     const uint32_t *cell_sorted, *cell_start;
     double *rho, *eps;
     int update_eps;
@@ -61,7 +61,7 @@ struct DensityF32Args {
 __device__ __forceinline__ void density_f32_body(const DensityF32Args &a, uint32_t blk)
 {
     const DevParams &P = a.P;
-    const float *__restrict__ qr = a.qr;
+    const float4 *__restrict__ qf = reinterpret_cast<const float4 *>(a.q4f);
     const uint32_t *__restrict__ cell_sorted = a.cell_sorted;
     const uint32_t *__restrict__ cell_start = a.cell_start;
     double *rho = a.rho, *eps = a.eps;
@@ -75,7 +75,8 @@ __device__ __forceinline__ void density_f32_body(const DensityF32Args &a, uint32
     const int cx = (int)(c % (uint32_t)P.nc[0]);
     const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
     const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
-    const float xi = qr[i], yi = qr[n + i], zi = qr[2 * n + i];
+    const float4 qi = qf[i];
+    const float xi = qi.x, yi = qi.y, zi = qi.z;
     float acc = 0.0f;
     for (int k = 0; k < 27; ++k) {
         const NbCellF nb = neighbour_cell_f32(P, cx, cy, cz, k);
@@ -87,9 +88,10 @@ __device__ __forceinline__ void density_f32_body(const DensityF32Args &a, uint32
             continue;
         }
         for (uint32_t j = s; j < e; ++j) {
-            const float dx = (xi - qr[j]) + nb.sx;
-            const float dy = (yi - qr[n + j]) + nb.sy;
-            const float dz = (zi - qr[2 * n + j]) + nb.sz;
+            const float4 qj = qf[j];
+            const float dx = (xi - qj.x) + nb.sx;
+            const float dy = (yi - qj.y) + nb.sy;
+            const float dz = (zi - qj.z) + nb.sz;
             const float r2 = dx * dx + dy * dy + dz * dz;
             if (r2 < P.h2_f) {
                 acc += P.m_f * kernel_w_f32(P, sqrtf(r2));
@@ -113,15 +115,16 @@ __global__ __launch_bounds__(256) void k_density_f32(DensityF32Args a)
 }
 SDPD_MULTI_KERNEL(k_density_f32_multi, DensityF32Args, density_f32_body, 256)
 
+// P_i / rho_i^2 into the w slot of the particle's FP32 record
 struct PressureF32Args {
     DevParams P;
     const double *eps, *rho;
-    float *pi_f;
+    float *q4f;
 };
 __device__ __forceinline__ void pressure_term_f32_body(const PressureF32Args &a, uint32_t blk)
 {
     int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
-    if (i < a.P.n) a.pi_f[i] = (float)(a.P.cPi * a.eps[i] / a.rho[i]);
+    if (i < a.P.n) a.q4f[4 * i + 3] = (float)(a.P.cPi * a.eps[i] / a.rho[i]);
 }
 __global__ void k_pressure_term_f32(PressureF32Args a) { pressure_term_f32_body(a, blockIdx.x); }
 SDPD_MULTI_KERNEL(k_pressure_term_f32_multi, PressureF32Args, pressure_term_f32_body, 256)
@@ -129,7 +132,7 @@ SDPD_MULTI_KERNEL(k_pressure_term_f32_multi, PressureF32Args, pressure_term_f32_
 // f_i over the partners recorded by the density pass, FP32 terms and sums
 struct ForcesF32Args {
     DevParams P;
-    const float *qr, *pi_f;
+    const float *q4f;
     const uint32_t *cell_sorted, *cell_start;
     const uint64_t *masks;
     double *f, *p;
@@ -138,8 +141,7 @@ struct ForcesF32Args {
 __device__ __forceinline__ void forces_f32_body(const ForcesF32Args &a, uint32_t blk)
 {
     const DevParams &P = a.P;
-    const float *__restrict__ qr = a.qr;
-    const float *__restrict__ pi_f = a.pi_f;
+    const float4 *__restrict__ qf = reinterpret_cast<const float4 *>(a.q4f);
     const uint32_t *__restrict__ cell_sorted = a.cell_sorted;
     const uint32_t *__restrict__ cell_start = a.cell_start;
     const uint64_t *__restrict__ masks = a.masks;
@@ -152,27 +154,58 @@ __device__ __forceinline__ void forces_f32_body(const ForcesF32Args &a, uint32_t
     const int cx = (int)(c % (uint32_t)P.nc[0]);
     const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
     const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
-    const float xi = qr[i], yi = qr[n + i], zi = qr[2 * n + i];
-    const float pii = pi_f[i];
+    const float4 qi = qf[i];
+    const float xi = qi.x, yi = qi.y, zi = qi.z, pii = qi.w;
     const float m2 = P.m_f * P.m_f;
-    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    // one loop over the lane's partners in the fixed order, moving on to the
+    // next non-empty neighbour cell inside the loop body (that cell's start
+    // and mask loaded one cell ahead), as in the FP64 force pass
+    uint32_t todo = 0u;
+    int total = 0;
     for (int k = 0; k < 27; ++k) {
-        uint64_t mask = masks[(int64_t)k * n + i];
-        if (!mask) continue;
+        const uint64_t m = masks[(int64_t)k * n + i];
+        todo |= (m != 0ull ? 1u : 0u) << k;
+        total += __popcll(m);
+    }
+    auto cell = [&](int k, uint32_t &start, uint64_t &m, float &hx, float &hy, float &hz) {
         const NbCellF nb = neighbour_cell_f32(P, cx, cy, cz, k);
-        const uint32_t s = cell_start[nb.c];
-        while (mask) {
-            const uint32_t j = s + (uint32_t)__builtin_ctzll(mask);
-            mask &= mask - 1ull;
-            const float dx = (xi - qr[j]) + nb.sx;
-            const float dy = (yi - qr[n + j]) + nb.sy;
-            const float dz = (zi - qr[2 * n + j]) + nb.sz;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float sc = m2 * (pii + pi_f[j]) * kernel_f_f32(P, sqrtf(r2));
-            fx += sc * dx;
-            fy += sc * dy;
-            fz += sc * dz;
+        hx = nb.sx;
+        hy = nb.sy;
+        hz = nb.sz;
+        start = cell_start[nb.c];
+        m = masks[(int64_t)k * n + i];
+    };
+    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    uint64_t mask = 0ull, mn = 0ull;
+    uint32_t s = 0u, sn = 0u;
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f, shx = 0.0f, shy = 0.0f, shz = 0.0f;
+    if (todo) {
+        cell(__builtin_ctz(todo), sn, mn, shx, shy, shz);
+        todo &= todo - 1u;
+    }
+    for (int t = 0; t < total; ++t) {
+        if (mask == 0ull) {
+            s = sn;
+            mask = mn;
+            sx = shx;
+            sy = shy;
+            sz = shz;
+            if (todo) {
+                cell(__builtin_ctz(todo), sn, mn, shx, shy, shz);
+                todo &= todo - 1u;
+            }
         }
+        const uint32_t j = s + (uint32_t)__builtin_ctzll(mask);
+        mask &= mask - 1ull;
+        const float4 qj = qf[j];
+        const float dx = (xi - qj.x) + sx;
+        const float dy = (yi - qj.y) + sy;
+        const float dz = (zi - qj.z) + sz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float sc = m2 * (pii + qj.w) * kernel_f_f32(P, sqrtf(r2));
+        fx += sc * dx;
+        fy += sc * dy;
+        fz += sc * dz;
     }
     const double gx = fx, gy = fy, gz = fz;
     f[i] = gx;
@@ -196,7 +229,7 @@ int run_density_f32(sdpd_ctx *c, const sdpd_state *s, int update_eps)
     timer_begin(c, TK_DENSITY);
     const int rc = launch_or_record(c, k_density_f32, k_density_f32_multi,
                                     (unsigned)((c->n + 255) / 256), 256, 0,
-                                    DensityF32Args{c->dp, c->qr, c->cell_sorted, c->cell_start,
+                                    DensityF32Args{c->dp, c->q4f, c->cell_sorted, c->cell_start,
                                                    s->rho, s->eps, update_eps, c->masks, c->err});
     timer_end(c, TK_DENSITY);
     return rc;
@@ -207,10 +240,10 @@ int run_forces_f32(sdpd_ctx *c, const sdpd_state *s, int half_kick)
     const unsigned g = (unsigned)((c->n + 255) / 256);
     timer_begin(c, TK_FORCE);
     int rc = launch_or_record(c, k_pressure_term_f32, k_pressure_term_f32_multi, g, 256, 0,
-                              PressureF32Args{c->dp, s->eps, s->rho, c->pi_f});
+                              PressureF32Args{c->dp, s->eps, s->rho, c->q4f});
     if (!rc)
         rc = launch_or_record(c, k_forces_f32, k_forces_f32_multi, g, 256, 0,
-                              ForcesF32Args{c->dp, c->qr, c->pi_f, c->cell_sorted, c->cell_start,
+                              ForcesF32Args{c->dp, c->q4f, c->cell_sorted, c->cell_start,
                                             c->masks, s->f, s->p, half_kick});
     timer_end(c, TK_FORCE);
     return rc;

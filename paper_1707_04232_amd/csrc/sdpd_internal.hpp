@@ -132,7 +132,7 @@ struct sdpd_ctx {
     double *tq, *tp, *teps, *trho, *tf;
     uint32_t *tid;
     double *q4;                  // (x, y, z, P/rho^2) per particle in cell order, 32 B
-    float *qr, *pi_f;            // mixed precision: positions relative to the cell, P/rho^2
+    float *q4f;                  // mixed precision: (x, y, z) relative to the cell, P/rho^2
     uint64_t *masks;             // NNB * n
     unsigned long long *counters;
     uint32_t *err;
