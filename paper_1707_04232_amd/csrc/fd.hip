@@ -353,7 +353,10 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
                                 i1 = t;
                             }
                             double d[4];
-                            pair_draws_stored(P, step, i0, i1, d);
+                            if (K == 2)   // mixed precision: FP32 Box-Muller
+                                pair_draws_f32(P, step, i0, i1, d);
+                            else
+                                pair_draws_stored(P, step, i0, i1, d);
                             double2 *dst = reinterpret_cast<double2 *>(wdraws) + 2 * (int64_t)e;
                             dst[0] = make_double2(d[0], d[1]);
                             dst[1] = make_double2(d[2], d[3]);

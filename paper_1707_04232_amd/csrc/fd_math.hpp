@@ -55,6 +55,45 @@ __device__ __forceinline__ void pair_draws(const DevParams &P, uint32_t step, ui
     U = open_unit(b0);
 }
 
+// Mixed precision: the Gaussian vector from the same Philox words through
+// Box-Muller in FP32.  The radius sqrt(-2 ln u) takes ln u as log1p(-(1 - u))
+// for u > 1/2, with 1 - u formed from the complement word, so that u near 1
+// keeps its relative precision (log1p(x) = ln(1 + x) x / ((1 + x) - 1)
+// compensates the rounding of 1 + x); the angles 2 pi t go to the hardware
+// sine and cosine, whose argument is in turns.  U stays the FP64 uniform.
+__device__ __forceinline__ float radius_f32(uint32_t w)
+{
+    const bool hi = w >= 0x80000000u;
+    const float v = ((float)(hi ? ~w : w) + 0.5f) * 2.3283064365386963e-10f;   // u or 1 - u
+    const float y = 1.0f - v;
+    const float l1 = y == 1.0f ? -v : __logf(y) * (-v / (y - 1.0f));
+    const float l = hi ? l1 : __logf(v);
+    return sqrtf(-2.0f * l);
+}
+__device__ __forceinline__ float turns_f32(uint32_t w)
+{
+    return ((float)w + 0.5f) * 2.3283064365386963e-10f;
+}
+__device__ __forceinline__ void gauss3_f32(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3,
+                                           double G[3])
+{
+    const float R1 = radius_f32(a0), R2 = radius_f32(a2);
+    const float t1 = turns_f32(a1), t3 = turns_f32(a3);
+    G[0] = (double)(R1 * __builtin_amdgcn_cosf(t1));
+    G[1] = (double)(R1 * __builtin_amdgcn_sinf(t1));
+    G[2] = (double)(R2 * __builtin_amdgcn_cosf(t3));
+}
+__device__ __forceinline__ void pair_draws_f32(const DevParams &P, uint32_t step, uint32_t id_i,
+                                               uint32_t id_j, double out[4])
+{
+    uint32_t a0 = step, a1 = id_i, a2 = id_j, a3 = P.replica * 2u;
+    uint32_t b0 = step, b1 = id_i, b2 = id_j, b3 = P.replica * 2u + 1u;
+    philox4x32_10(a0, a1, a2, a3, P.seed_lo, P.seed_hi);
+    philox4x32_10(b0, b1, b2, b3, P.seed_lo, P.seed_hi);
+    gauss3_f32(a0, a1, a2, a3, out);
+    out[3] = open_unit(b0);
+}
+
 // ---------------------------------------------------------------- coefficients
 // alpha^theta and the squared relative-velocity noise amplitude
 // b^theta^2 = ((2/m) zeta^theta)^2 at energies (ei, ej).  With
