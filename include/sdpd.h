@@ -55,12 +55,14 @@ typedef enum { SDPD_FD_EMS = 0, SDPD_FD_AMS = 1, SDPD_FD_SSA = 2, SDPD_FD_NONE =
 /* arithmetic of the particle passes: everything in FP64, or (MIXED) the
  * density, the pair masks and the pressure forces from FP32 positions
  * relative to the particle's cell, FP32 kernel values and FP32 sums, and
- * (EMS with Lucy's kernel and zeta = 0) the F/D pair geometry and the
- * proposal coefficients alpha, b of eq. (proposal) in FP32, while momenta,
- * energies, the equation of state, the proposal v' = alpha v + b G, Delta,
- * the Metropolis ratio (evaluated for those same coefficients) and the
- * observables stay FP64.  MIXED decides r < h in FP32, so pairs within
- * ~1e-7 h of the cutoff may differ from FP64.                             */
+ * (EMS with Lucy's kernel and zeta = 0) the F/D pair geometry, the Gaussian
+ * draws G (Box-Muller of the same Philox words) and the proposal
+ * coefficients alpha, b of eq. (proposal) in FP32, while momenta, energies,
+ * the equation of state, the uniform U, the proposal v' = alpha v + b G,
+ * Delta, the Metropolis ratio (evaluated for those same coefficients and
+ * draws) and the observables stay FP64.  MIXED decides r < h in FP32, so
+ * pairs within ~1e-7 h of the cutoff may differ from FP64; its draws lie
+ * within ~2e-6 of the FP64 ones.                                          */
 typedef enum { SDPD_FP64 = 0, SDPD_MIXED = 1 } sdpd_prec;
 
 /* Physical and numerical parameters.  Ideal-gas entropy closure
