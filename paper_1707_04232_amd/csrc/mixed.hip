@@ -138,44 +138,45 @@ struct ForcesF32Args {
     double *f, *p;
     int half_kick;
 };
-__device__ __forceinline__ void forces_f32_body(const ForcesF32Args &a, uint32_t blk)
+// One loop over the lane's partners in the fixed order, moving on to the
+// next non-empty neighbour cell inside the loop body (that cell's start and
+// mask loaded one cell ahead), as in the FP64 force pass.  EDGE: some lane of
+// the wave sits in a first or last cell of an axis, where the neighbour index
+// wraps; elsewhere cell k is c + o_x + o_y n_x + o_z n_x n_y - (1 + n_x +
+// n_x n_y) for the offset digits o of k.  The shift -(o - 1) * cell edge is
+// the same in both cases (positions are relative to the cell).
+template <bool EDGE>
+__device__ __forceinline__ void forces_f32_loop(const DevParams &P, const float4 *__restrict__ qf,
+                                                const uint32_t *__restrict__ cell_start,
+                                                const uint64_t *__restrict__ masks, int64_t i,
+                                                uint32_t c, int cx, int cy, int cz, uint32_t todo,
+                                                int total, float4 qi, float &fx, float &fy,
+                                                float &fz)
 {
-    const DevParams &P = a.P;
-    const float4 *__restrict__ qf = reinterpret_cast<const float4 *>(a.q4f);
-    const uint32_t *__restrict__ cell_sorted = a.cell_sorted;
-    const uint32_t *__restrict__ cell_start = a.cell_start;
-    const uint64_t *__restrict__ masks = a.masks;
-    double *f = a.f, *p = a.p;
-    const int half_kick = a.half_kick;
-    const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
-    if (i >= P.n) return;
     const int64_t n = P.n;
-    const uint32_t c = cell_sorted[i];
-    const int cx = (int)(c % (uint32_t)P.nc[0]);
-    const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
-    const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
-    const float4 qi = qf[i];
+    const uint32_t nx = (uint32_t)P.nc[0], nxy = nx * (uint32_t)P.nc[1];
+    const uint32_t c0 = c - 1u - nx - nxy;
     const float xi = qi.x, yi = qi.y, zi = qi.z, pii = qi.w;
     const float m2 = P.m_f * P.m_f;
-    // one loop over the lane's partners in the fixed order, moving on to the
-    // next non-empty neighbour cell inside the loop body (that cell's start
-    // and mask loaded one cell ahead), as in the FP64 force pass
-    uint32_t todo = 0u;
-    int total = 0;
-    for (int k = 0; k < 27; ++k) {
-        const uint64_t m = masks[(int64_t)k * n + i];
-        todo |= (m != 0ull ? 1u : 0u) << k;
-        total += __popcll(m);
-    }
     auto cell = [&](int k, uint32_t &start, uint64_t &m, float &hx, float &hy, float &hz) {
-        const NbCellF nb = neighbour_cell_f32(P, cx, cy, cz, k);
-        hx = nb.sx;
-        hy = nb.sy;
-        hz = nb.sz;
-        start = cell_start[nb.c];
+        uint32_t cn;
+        if (EDGE) {
+            const NbCellF nb = neighbour_cell_f32(P, cx, cy, cz, k);
+            cn = (uint32_t)nb.c;
+            hx = nb.sx;
+            hy = nb.sy;
+            hz = nb.sz;
+        } else {
+            const uint32_t q3 = ((uint32_t)k * 11u) >> 5;   // k / 3 for k < 27
+            const uint32_t o0 = (uint32_t)k - 3u * q3, o2 = (q3 * 11u) >> 5, o1 = q3 - 3u * o2;
+            cn = c0 + o0 + o1 * nx + o2 * nxy;
+            hx = -(float)((int)o0 - 1) * P.cell_f[0];
+            hy = -(float)((int)o1 - 1) * P.cell_f[1];
+            hz = -(float)((int)o2 - 1) * P.cell_f[2];
+        }
+        start = cell_start[cn];
         m = masks[(int64_t)k * n + i];
     };
-    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     uint64_t mask = 0ull, mn = 0ull;
     uint32_t s = 0u, sn = 0u;
     float sx = 0.0f, sy = 0.0f, sz = 0.0f, shx = 0.0f, shy = 0.0f, shz = 0.0f;
@@ -184,7 +185,7 @@ __device__ __forceinline__ void forces_f32_body(const ForcesF32Args &a, uint32_t
         todo &= todo - 1u;
     }
     for (int t = 0; t < total; ++t) {
-        if (mask == 0ull) {
+        if (mask == 0ull) {   // the prefetched cell becomes current
             s = sn;
             mask = mn;
             sx = shx;
@@ -207,11 +208,43 @@ __device__ __forceinline__ void forces_f32_body(const ForcesF32Args &a, uint32_t
         fy += sc * dy;
         fz += sc * dz;
     }
+}
+
+__device__ __forceinline__ void forces_f32_body(const ForcesF32Args &a, uint32_t blk)
+{
+    const DevParams &P = a.P;
+    const float4 *__restrict__ qf = reinterpret_cast<const float4 *>(a.q4f);
+    const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const int64_t n = P.n;
+    const uint32_t c = a.cell_sorted[i];
+    const int cx = (int)(c % (uint32_t)P.nc[0]);
+    const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
+    const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
+    const float4 qi = qf[i];
+    // non-empty neighbour cells (bit k) and the number of partners
+    uint32_t todo = 0u;
+    int total = 0;
+    for (int k = 0; k < 27; ++k) {
+        const uint64_t m = a.masks[(int64_t)k * n + i];
+        todo |= (m != 0ull ? 1u : 0u) << k;
+        total += __popcll(m);
+    }
+    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    const bool edge = cx == 0 || cy == 0 || cz == 0 || cx == P.nc[0] - 1 || cy == P.nc[1] - 1 ||
+                      cz == P.nc[2] - 1;
+    if (__ballot(edge))
+        forces_f32_loop<true>(P, qf, a.cell_start, a.masks, i, c, cx, cy, cz, todo, total, qi, fx,
+                              fy, fz);
+    else
+        forces_f32_loop<false>(P, qf, a.cell_start, a.masks, i, c, cx, cy, cz, todo, total, qi, fx,
+                               fy, fz);
     const double gx = fx, gy = fy, gz = fz;
+    double *f = a.f, *p = a.p;
     f[i] = gx;
     f[n + i] = gy;
     f[2 * n + i] = gz;
-    if (half_kick) {
+    if (a.half_kick) {
         const double hd = 0.5 * P.dt;
         p[i] += hd * gx;
         p[n + i] += hd * gy;
