@@ -73,6 +73,28 @@ __device__ __forceinline__ double fd_expm1(double x)
     return fma(t, p, t - 1.0);
 }
 
+// expm1(x) for |x| <= 2^-5: its Taylor polynomial to x^8 (the first term
+// left out, x^9/9!, is below 2^-58 |x| there)
+__device__ __forceinline__ double fd_expm1_small(double x)
+{
+    double p = 2.48015873015873e-05;      // 1/8!
+    p = fma(p, x, 0.0001984126984126984);  // 1/7!
+    p = fma(p, x, 0.001388888888888889);   // 1/6!
+    p = fma(p, x, 0.008333333333333333);   // 1/5!
+    p = fma(p, x, 0.041666666666666664);   // 1/4!
+    p = fma(p, x, 0.16666666666666666);    // 1/3!
+    p = fma(p, x, 0.5);
+    return fma(p * x, x, x);               // x + x^2 (1/2 + x/6 + ...)
+}
+
+// expm1 with the short form when no active lane of the wave has |x| > 2^-5
+// (the friction exponents of a step of ordinary size), else fd_expm1
+__device__ __forceinline__ double fd_expm1_wave(double x)
+{
+    if (__ballot(fabs(x) > 0x1p-5) == 0ull) return fd_expm1_small(x);
+    return fd_expm1(x);
+}
+
 __device__ __forceinline__ double fd_log(double x)
 {
     int e;

@@ -121,8 +121,9 @@ __device__ __forceinline__ Coef fd_coef(const DevParams &P, const R &pr, double 
     const double d = pr.kB * Tred * inv_Ts * pr.two_over_Cv;
     const double omd = 1.0 - d;
     const double c = -2.0 * dt * pr.inv_m * omd;
-    const double e_perp = fd_expm1(c * kperp);
-    const double e_par = (FAST || P.par_twice_perp) ? e_perp * (2.0 + e_perp) : fd_expm1(c * kpar);
+    const double e_perp = fd_expm1_wave(c * kperp);
+    const double e_par =
+        (FAST || P.par_twice_perp) ? e_perp * (2.0 + e_perp) : fd_expm1_wave(c * kpar);
     const double s = pr.b2_c * Tred * fast_rcp(omd);
     Coef r;
     r.al_par = 1.0 + e_par;

@@ -57,6 +57,10 @@ CASES = {
     "ragged_box": lambda: (*uniform_state(1500, (10.0, 12.5, 15.0), seed=2), (10.0, 12.5, 15.0)),
     "dilute": lambda: (*uniform_state(300, (20.0, 20.0, 20.0), seed=3), 20.0),
     "lattice24x20x16": lambda: (*lattice_state((24, 20, 16), Cv=1.5, T=0.1), (24.0, 20.0, 16.0)),
+    # 12 cells per axis: waves whose 64 particles all sit in interior cells
+    # (the force pass's wrap-free neighbour index) beside waves with a lane
+    # in a first or last cell
+    "lattice32": lambda: (*lattice_state(32, Cv=1.5, T=0.1), 32.0),
 }
 
 
