@@ -14,12 +14,15 @@
 //   * sin(pi t), cos(pi t): t reduced by multiples of 1/2 to |r| <= 1/4,
 //     Taylor polynomials of sin(pi r) and cos(pi r) to degree 19 / 18, then a
 //     quarter-turn rotation.
-//   * sqrt: reciprocal square root estimate with two Newton steps, one
-//     Newton correction of the product.
+//   * reciprocal and reciprocal square root: the hardware estimate (relative
+//     error below 6e-8) and one second-order correction; sqrt: the
+//     reciprocal square root and one Newton correction of the product.
 //   * expm1: x = k ln 2 + r with |r| <= ln 2 / 2 (two-part ln 2), the Taylor
 //     polynomial of expm1(r) to degree 13 (its tail is below 2^-53 |r|), and
 //     expm1(x) = 2^k expm1(r) + (2^k - 1) in one fused step; for |x| <= ln 2 / 2
-//     k = 0 and the polynomial alone is the result.
+//     k = 0 and the polynomial alone is the result.  When no active lane of
+//     a wave has |x| > 2^-5 the wave takes the Taylor polynomial of expm1(x)
+//     to degree 8 instead.
 #pragma once
 
 namespace sdpd {
