@@ -145,19 +145,28 @@ __device__ __forceinline__ void forces_body(const ForcesArgs &a, uint32_t blk)
     const uint32_t nx = (uint32_t)P.nc[0], ny = (uint32_t)P.nc[1];
     const NbSteps nb(P, (int)(c % nx), (int)((c / nx) % ny), (int)(c / (nx * ny)));
     const double4 qi = reinterpret_cast<const double4 *>(a.q4)[i];
-    // non-empty neighbour cells (bit k) and the number of partners
-    uint32_t todo = 0u;
-    int total = 0;
-    for (int k = 0; k < 27; ++k) {
-        const uint64_t m = a.masks[(int64_t)k * n + i];
-        todo |= (m != 0ull ? 1u : 0u) << k;
-        total += __popcll(m);
-    }
+    const bool edge = __ballot((nb.lo | nb.hi) != 0u) != 0ull;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (__ballot((nb.lo | nb.hi) != 0u))
-        forces_flat_loop<true>(P, a.q4, a.cell_start, a.masks, i, c, nb, todo, total, qi, fx, fy, fz);
-    else
-        forces_flat_loop<false>(P, a.q4, a.cell_start, a.masks, i, c, nb, todo, total, qi, fx, fy, fz);
+    // one loop per layer of nine neighbour cells (offsets 9l .. 9l + 8, equal
+    // z offset), so that the lanes of a wave read the records of nearby cells
+    // at about the same time (same sums in the same order as one loop)
+    constexpr int kGroups = 3, kPer = 27 / kGroups;
+    for (int g = 0; g < kGroups; ++g) {
+        // non-empty neighbour cells (bit k) and the number of partners
+        uint32_t todo = 0u;
+        int total = 0;
+        for (int k = g * kPer; k < (g + 1) * kPer; ++k) {
+            const uint64_t m = a.masks[(int64_t)k * n + i];
+            todo |= (m != 0ull ? 1u : 0u) << k;
+            total += __popcll(m);
+        }
+        if (edge)
+            forces_flat_loop<true>(P, a.q4, a.cell_start, a.masks, i, c, nb, todo, total, qi, fx,
+                                   fy, fz);
+        else
+            forces_flat_loop<false>(P, a.q4, a.cell_start, a.masks, i, c, nb, todo, total, qi, fx,
+                                    fy, fz);
+    }
     double *f = a.f, *p = a.p;
     f[i] = fx;
     f[n + i] = fy;

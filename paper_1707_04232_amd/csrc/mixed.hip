@@ -222,23 +222,27 @@ __device__ __forceinline__ void forces_f32_body(const ForcesF32Args &a, uint32_t
     const int cy = (int)((c / (uint32_t)P.nc[0]) % (uint32_t)P.nc[1]);
     const int cz = (int)(c / ((uint32_t)P.nc[0] * (uint32_t)P.nc[1]));
     const float4 qi = qf[i];
-    // non-empty neighbour cells (bit k) and the number of partners
-    uint32_t todo = 0u;
-    int total = 0;
-    for (int k = 0; k < 27; ++k) {
-        const uint64_t m = a.masks[(int64_t)k * n + i];
-        todo |= (m != 0ull ? 1u : 0u) << k;
-        total += __popcll(m);
-    }
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    const bool edge = cx == 0 || cy == 0 || cz == 0 || cx == P.nc[0] - 1 || cy == P.nc[1] - 1 ||
-                      cz == P.nc[2] - 1;
-    if (__ballot(edge))
-        forces_f32_loop<true>(P, qf, a.cell_start, a.masks, i, c, cx, cy, cz, todo, total, qi, fx,
-                              fy, fz);
-    else
-        forces_f32_loop<false>(P, qf, a.cell_start, a.masks, i, c, cx, cy, cz, todo, total, qi, fx,
-                               fy, fz);
+    const bool edge = __ballot(cx == 0 || cy == 0 || cz == 0 || cx == P.nc[0] - 1 ||
+                               cy == P.nc[1] - 1 || cz == P.nc[2] - 1) != 0ull;
+    // one loop per layer of nine neighbour cells, as in the FP64 force pass
+    constexpr int kGroups = 3, kPer = 27 / kGroups;
+    for (int g = 0; g < kGroups; ++g) {
+        // non-empty neighbour cells (bit k) and the number of partners
+        uint32_t todo = 0u;
+        int total = 0;
+        for (int k = g * kPer; k < (g + 1) * kPer; ++k) {
+            const uint64_t m = a.masks[(int64_t)k * n + i];
+            todo |= (m != 0ull ? 1u : 0u) << k;
+            total += __popcll(m);
+        }
+        if (edge)
+            forces_f32_loop<true>(P, qf, a.cell_start, a.masks, i, c, cx, cy, cz, todo, total, qi,
+                                  fx, fy, fz);
+        else
+            forces_f32_loop<false>(P, qf, a.cell_start, a.masks, i, c, cx, cy, cz, todo, total, qi,
+                                   fx, fy, fz);
+    }
     const double gx = fx, gy = fy, gz = fz;
     double *f = a.f, *p = a.p;
     f[i] = gx;
