@@ -114,7 +114,10 @@ __device__ __forceinline__ void density_body(const DensityArgs &a, uint32_t blk)
         eps[i] = e_new;
     }
 }
-__global__ __launch_bounds__(256) void k_density(DensityArgs a) { density_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_density(DensityArgs a)
+{
+    density_body(a, xcd_block(blockIdx.x, gridDim.x));
+}
 SDPD_MULTI_KERNEL(k_density_multi, DensityArgs, density_body, 256)
 
 // The same pass with four lanes per particle, for boxes too small to fill
@@ -225,7 +228,7 @@ __device__ __forceinline__ void density_quad_body(const DensityArgs &a, uint32_t
 }
 __global__ __launch_bounds__(256) void k_density_quad(DensityArgs a)
 {
-    density_quad_body(a, blockIdx.x);
+    density_quad_body(a, xcd_block(blockIdx.x, gridDim.x));
 }
 SDPD_MULTI_KERNEL(k_density_quad_multi, DensityArgs, density_quad_body, 256)
 

@@ -178,7 +178,10 @@ __device__ __forceinline__ void forces_body(const ForcesArgs &a, uint32_t blk)
         p[2 * n + i] += hd * fz;
     }
 }
-__global__ __launch_bounds__(256) void k_forces(ForcesArgs a) { forces_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_forces(ForcesArgs a)
+{
+    forces_body(a, xcd_block(blockIdx.x, gridDim.x));
+}
 SDPD_MULTI_KERNEL(k_forces_multi, ForcesArgs, forces_body, 256)
 
 int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick)

@@ -111,7 +111,7 @@ __device__ __forceinline__ void density_f32_body(const DensityF32Args &a, uint32
 }
 __global__ __launch_bounds__(256) void k_density_f32(DensityF32Args a)
 {
-    density_f32_body(a, blockIdx.x);
+    density_f32_body(a, xcd_block(blockIdx.x, gridDim.x));
 }
 SDPD_MULTI_KERNEL(k_density_f32_multi, DensityF32Args, density_f32_body, 256)
 
@@ -257,7 +257,7 @@ __device__ __forceinline__ void forces_f32_body(const ForcesF32Args &a, uint32_t
 }
 __global__ __launch_bounds__(256) void k_forces_f32(ForcesF32Args a)
 {
-    forces_f32_body(a, blockIdx.x);
+    forces_f32_body(a, xcd_block(blockIdx.x, gridDim.x));
 }
 SDPD_MULTI_KERNEL(k_forces_f32_multi, ForcesF32Args, forces_f32_body, 256)
 

@@ -107,6 +107,26 @@ using LaunchRecord = std::vector<RecordedLaunch>;
 // (the table is read-only for the whole launch: restrict lets the compiler
 // keep argument fields across the body's stores, as it does for kernel
 // arguments)
+// The chip deals workgroups to its 8 XCDs in turn (workgroup b to XCD
+// b mod 8), each XCD with an L2 of its own.  xcd_block(b, n) renumbers the n
+// workgroups of a grid so that each XCD takes runs of kRun consecutive
+// workgroups (of every 8 kRun, the x-th run to XCD x): in cell order, the
+// cells a particle pass reads around its own are then more often in the L2
+// of the XCD that reads them, while the eight XCDs still work on nearby
+// parts of the grid (one contiguous eighth per XCD helped a 2^20-particle box
+// and hurt an 8M one, whose eight fronts no longer shared the last-level
+// cache).  The trailing n mod 8 kRun workgroups keep their numbers.  A
+// bijection onto [0, n) for any n (on a chip with another XCD count only the
+// locality differs).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n)
+{
+    constexpr uint32_t kXcd = 8, kRun = 32;
+    const uint32_t span = kXcd * kRun, full = n / span * span;
+    if (b >= full) return b;
+    const uint32_t base = b / span * span, o = b - base;
+    return base + (o % kXcd) * kRun + o / kXcd;
+}
+
 #define SDPD_MULTI_KERNEL(NAME, ARGS, BODY, THREADS)                                          \
     __global__ __launch_bounds__(THREADS) void NAME(const void *__restrict__ tab,              \
                                                     const uint2 *__restrict__ wg)              \
