@@ -75,7 +75,7 @@ __device__ __forceinline__ void task_count_body(const TaskCountArgs &a, uint32_t
 }
 __global__ __launch_bounds__(64 * COUNT_WAVES) void k_task_count(TaskCountArgs a)
 {
-    task_count_body(a, blockIdx.x);
+    task_count_body(a, xcd_block(blockIdx.x, gridDim.x));
 }
 SDPD_MULTI_KERNEL(k_task_count_multi, TaskCountArgs, task_count_body, 64 * COUNT_WAVES)
 
@@ -266,7 +266,7 @@ __device__ __forceinline__ void schedule_body(const ScheduleArgs &a, uint32_t bl
 
 __global__ __launch_bounds__(64 * SCHED_WAVES) void k_schedule(ScheduleArgs a)
 {
-    schedule_body(a, blockIdx.x);
+    schedule_body(a, xcd_block(blockIdx.x, gridDim.x));
 }
 SDPD_MULTI_KERNEL(k_schedule_multi, ScheduleArgs, schedule_body, 64 * SCHED_WAVES)
 
