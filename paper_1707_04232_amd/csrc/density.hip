@@ -37,7 +37,7 @@ __device__ __forceinline__ uint64_t density_cell(const DevParams &P, const doubl
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < P.h2) {
             // r = 0 (i itself): sqrt(DBL_MIN) gives the same W as r = 0, exactly
-            acc += P.m * kernel_w(P, fd_sqrt(fmax(r2, DBL_MIN)));
+            acc += P.m * kernel_w(P, fd_sqrt_pair(fmax(r2, DBL_MIN)));
             mask |= bit;
         }
     }
@@ -152,7 +152,7 @@ __device__ __forceinline__ uint64_t density_cell_quad(const DevParams &P,
             }
             const double r2 = dx * dx + dy * dy + dz * dz;
             if (r2 < P.h2) {
-                w = P.m * kernel_w(P, fd_sqrt(fmax(r2, DBL_MIN)));
+                w = P.m * kernel_w(P, fd_sqrt_pair(fmax(r2, DBL_MIN)));
                 mask |= 1ull << jj;
             }
         }

@@ -48,6 +48,11 @@ __device__ __forceinline__ double fast_rsq(double x)
     return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
+// sqrt(x) as x / sqrt(x) from the reciprocal square root alone (within
+// about two ulp): the pair distances of the particle passes, whose kernel
+// values tolerate it
+__device__ __forceinline__ double fd_sqrt_pair(double x) { return x * fast_rsq(x); }
+
 __device__ __forceinline__ double fd_sqrt(double x)
 {
     const double y = fast_rsq(x);

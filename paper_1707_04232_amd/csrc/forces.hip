@@ -128,7 +128,7 @@ __device__ __forceinline__ void forces_flat_loop(const DevParams &P, const doubl
         const double dz = EDGE ? (zi - qj.z) + sz : zi - qj.z;
         const double r2 = dx * dx + dy * dy + dz * dz;
         // coincident particles (r = 0): F(sqrt(DBL_MIN)) = F(0) and dx = 0
-        const double sc = m2 * (pii + qj.w) * kernel_f(P, fd_sqrt(fmax(r2, DBL_MIN)));
+        const double sc = m2 * (pii + qj.w) * kernel_f(P, fd_sqrt_pair(fmax(r2, DBL_MIN)));
         fx += sc * dx;
         fy += sc * dy;
         fz += sc * dz;
