@@ -228,7 +228,7 @@ __device__ __forceinline__ void density_quad_body(const DensityArgs &a, uint32_t
 }
 __global__ __launch_bounds__(256) void k_density_quad(DensityArgs a)
 {
-    density_quad_body(a, xcd_block(blockIdx.x, gridDim.x));
+    density_quad_body(a, blockIdx.x);
 }
 SDPD_MULTI_KERNEL(k_density_quad_multi, DensityArgs, density_quad_body, 256)
 

@@ -135,6 +135,7 @@ __device__ __forceinline__ void forces_flat_loop(const DevParams &P, const doubl
     }
 }
 
+template <int G>
 __device__ __forceinline__ void forces_body(const ForcesArgs &a, uint32_t blk)
 {
     const DevParams &P = a.P;
@@ -147,10 +148,11 @@ __device__ __forceinline__ void forces_body(const ForcesArgs &a, uint32_t blk)
     const double4 qi = reinterpret_cast<const double4 *>(a.q4)[i];
     const bool edge = __ballot((nb.lo | nb.hi) != 0u) != 0ull;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    // one loop per layer of nine neighbour cells (offsets 9l .. 9l + 8, equal
-    // z offset), so that the lanes of a wave read the records of nearby cells
-    // at about the same time (same sums in the same order as one loop)
-    constexpr int kGroups = 3, kPer = 27 / kGroups;
+    // G = 3: one loop per layer of nine neighbour cells (offsets 9l .. 9l + 8,
+    // equal z offset), so that the lanes of a wave read the records of nearby
+    // cells at about the same time; G = 1: one loop over all 27 (the same
+    // sums in the same order either way)
+    constexpr int kGroups = G, kPer = 27 / kGroups;
     for (int g = 0; g < kGroups; ++g) {
         // non-empty neighbour cells (bit k) and the number of partners
         uint32_t todo = 0u;
@@ -178,11 +180,18 @@ __device__ __forceinline__ void forces_body(const ForcesArgs &a, uint32_t blk)
         p[2 * n + i] += hd * fz;
     }
 }
+template <int G>
 __global__ __launch_bounds__(256) void k_forces(ForcesArgs a)
 {
-    forces_body(a, xcd_block(blockIdx.x, gridDim.x));
+    forces_body<G>(a, xcd_block(blockIdx.x, gridDim.x));
 }
-SDPD_MULTI_KERNEL(k_forces_multi, ForcesArgs, forces_body, 256)
+SDPD_MULTI_KERNEL(k_forces_multi, ForcesArgs, forces_body<1>, 256)
+
+// Boxes above 2^17 particles take one partner loop per layer of neighbour
+// cells; smaller boxes, whose few workgroups leave the pass latency-bound,
+// and the multi-box launches of batches (boxes of at most 64,000 particles)
+// one loop over all 27.
+constexpr int64_t kLayerMinParticles = (int64_t)1 << 17;
 
 int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick)
 {
@@ -193,7 +202,8 @@ int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick)
     int rc = launch_or_record(c, k_pressure_term, k_pressure_term_multi, g, 256, 0,
                               PressureArgs{c->dp, s->q, s->eps, s->rho, c->q4});
     if (!rc)
-        rc = launch_or_record(c, k_forces, k_forces_multi, g, 256, 0,
+        rc = launch_or_record(c, c->n > kLayerMinParticles ? k_forces<3> : k_forces<1>,
+                              k_forces_multi, g, 256, 0,
                               ForcesArgs{c->dp, c->q4, c->cell_sorted, c->cell_start, c->masks,
                                          s->f, s->p, half_kick});
     timer_end(c, TK_FORCE);

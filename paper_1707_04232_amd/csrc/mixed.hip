@@ -210,6 +210,7 @@ __device__ __forceinline__ void forces_f32_loop(const DevParams &P, const float4
     }
 }
 
+template <int G>
 __device__ __forceinline__ void forces_f32_body(const ForcesF32Args &a, uint32_t blk)
 {
     const DevParams &P = a.P;
@@ -225,8 +226,8 @@ __device__ __forceinline__ void forces_f32_body(const ForcesF32Args &a, uint32_t
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     const bool edge = __ballot(cx == 0 || cy == 0 || cz == 0 || cx == P.nc[0] - 1 ||
                                cy == P.nc[1] - 1 || cz == P.nc[2] - 1) != 0ull;
-    // one loop per layer of nine neighbour cells, as in the FP64 force pass
-    constexpr int kGroups = 3, kPer = 27 / kGroups;
+    // G loops over the neighbour cells, as in the FP64 force pass
+    constexpr int kGroups = G, kPer = 27 / kGroups;
     for (int g = 0; g < kGroups; ++g) {
         // non-empty neighbour cells (bit k) and the number of partners
         uint32_t todo = 0u;
@@ -255,11 +256,12 @@ __device__ __forceinline__ void forces_f32_body(const ForcesF32Args &a, uint32_t
         p[2 * n + i] += hd * gz;
     }
 }
+template <int G>
 __global__ __launch_bounds__(256) void k_forces_f32(ForcesF32Args a)
 {
-    forces_f32_body(a, xcd_block(blockIdx.x, gridDim.x));
+    forces_f32_body<G>(a, xcd_block(blockIdx.x, gridDim.x));
 }
-SDPD_MULTI_KERNEL(k_forces_f32_multi, ForcesF32Args, forces_f32_body, 256)
+SDPD_MULTI_KERNEL(k_forces_f32_multi, ForcesF32Args, forces_f32_body<1>, 256)
 
 int run_density_f32(sdpd_ctx *c, const sdpd_state *s, int update_eps)
 {
@@ -272,6 +274,9 @@ int run_density_f32(sdpd_ctx *c, const sdpd_state *s, int update_eps)
     return rc;
 }
 
+// boxes above 2^17 particles: one partner loop per layer of neighbour cells
+constexpr int64_t kLayerMinParticlesF32 = (int64_t)1 << 17;
+
 int run_forces_f32(sdpd_ctx *c, const sdpd_state *s, int half_kick)
 {
     const unsigned g = (unsigned)((c->n + 255) / 256);
@@ -279,7 +284,8 @@ int run_forces_f32(sdpd_ctx *c, const sdpd_state *s, int half_kick)
     int rc = launch_or_record(c, k_pressure_term_f32, k_pressure_term_f32_multi, g, 256, 0,
                               PressureF32Args{c->dp, s->eps, s->rho, c->q4f});
     if (!rc)
-        rc = launch_or_record(c, k_forces_f32, k_forces_f32_multi, g, 256, 0,
+        rc = launch_or_record(c, c->n > kLayerMinParticlesF32 ? k_forces_f32<3> : k_forces_f32<1>,
+                              k_forces_f32_multi, g, 256, 0,
                               ForcesF32Args{c->dp, c->q4f, c->cell_sorted, c->cell_start,
                                             c->masks, s->f, s->p, half_kick});
     timer_end(c, TK_FORCE);
