@@ -148,7 +148,7 @@ struct FdArgs {
 // everything before it (entries, lists, ids, positions, the draws) is fixed
 // during the sweep, so the level sort and the draws of a range overlap the
 // wait for its predecessors.
-template <int K, bool COHERENT, bool VREG, class Wait>
+template <int K, bool COHERENT, bool VREG, int SPL, class Wait>
 __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, int64_t b,
                                          unsigned char *lds, const FdArgs &A, FdCount &cnt,
                                          bool &negeps, Wait &wait)
@@ -370,15 +370,45 @@ __device__ __forceinline__ void fd_range(const DevParams &P, const FdLaunch &L, 
                 //      range's predecessors, on the first batch)
                 wait();
                 for (int base = 0; base < np; base += FD_PPL * FD_THREADS) {
+                    // SPL > 0: the loads of SPL particles issued before their
+                    // LDS writes (an LDS write between two atomic loads makes
+                    // the second wait for the first; plain loads the
+                    // compiler reorders by itself, SPL = 0)
+                    constexpr int SPB = SPL > 0 ? SPL : 1;
 #pragma unroll
-                    for (int r = 0; r < FD_PPL; ++r) {
-                        const int l = base + r * FD_THREADS + tid;
-                        if (l < np) {
-                            const int64_t g = s_gidx[l];
-                            s_p[l] = state_load<COHERENT>(p + g);
-                            s_p[CP + l] = state_load<COHERENT>(p + n + g);
-                            s_p[2 * CP + l] = state_load<COHERENT>(p + 2 * n + g);
-                            s_eps[l] = state_load<COHERENT>(eps + g);
+                    for (int r0 = 0; r0 < FD_PPL; r0 += SPB) {
+                        if (SPL == 0) {
+                            const int l = base + r0 * FD_THREADS + tid;
+                            if (l < np) {
+                                const int64_t g = s_gidx[l];
+                                s_p[l] = state_load<COHERENT>(p + g);
+                                s_p[CP + l] = state_load<COHERENT>(p + n + g);
+                                s_p[2 * CP + l] = state_load<COHERENT>(p + 2 * n + g);
+                                s_eps[l] = state_load<COHERENT>(eps + g);
+                            }
+                            continue;
+                        }
+                        double v[SPB][4];
+#pragma unroll
+                        for (int r = 0; r < SPB; ++r) {
+                            const int l = base + (r0 + r) * FD_THREADS + tid;
+                            if (l < np) {
+                                const int64_t g = s_gidx[l];
+                                v[r][0] = state_load<COHERENT>(p + g);
+                                v[r][1] = state_load<COHERENT>(p + n + g);
+                                v[r][2] = state_load<COHERENT>(p + 2 * n + g);
+                                v[r][3] = state_load<COHERENT>(eps + g);
+                            }
+                        }
+#pragma unroll
+                        for (int r = 0; r < SPB; ++r) {
+                            const int l = base + (r0 + r) * FD_THREADS + tid;
+                            if (l < np) {
+                                s_p[l] = v[r][0];
+                                s_p[CP + l] = v[r][1];
+                                s_p[2 * CP + l] = v[r][2];
+                                s_eps[l] = v[r][3];
+                            }
                         }
                     }
                 }
@@ -509,7 +539,7 @@ __device__ __forceinline__ void fd_phase_body(const FdPhaseArgs &a, uint32_t blk
     FdCount cnt = {0u, 0u, 0u, 0u, 0u};
     bool negeps = false;
     auto no_wait = [] {};
-    fd_range<K, false, K != 0>(*a.Pp, a.L, (int64_t)blk, lds, a.A, cnt, negeps, no_wait);
+    fd_range<K, false, K != 0, 0>(*a.Pp, a.L, (int64_t)blk, lds, a.A, cnt, negeps, no_wait);
     fd_flush_counters(cnt, negeps, a.counters, a.A.err);
 }
 template <int K>
@@ -545,7 +575,7 @@ constexpr uint64_t kWaitTicks = 20ull * 100000000ull;   // 20 s
 
 // One range of the one-launch sweep: range b of group g, waiting until the
 // cells of its tasks have epoch g and setting them to g + 1 afterwards.
-template <int K, bool VREG>
+template <int K, bool VREG, int SPL>
 __device__ __forceinline__ void fd_flow_range(const DevParams &P, const FdLaunch &L, int g,
                                               int64_t b, const FdArgs &A, uint32_t *epoch,
                                               unsigned char *lds, FdCount &cnt, bool &negeps)
@@ -596,7 +626,7 @@ __device__ __forceinline__ void fd_flow_range(const DevParams &P, const FdLaunch
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     };
-    fd_range<K, true, VREG>(P, L, b, lds, A, cnt, negeps, wait);
+    fd_range<K, true, VREG, SPL>(P, L, b, lds, A, cnt, negeps, wait);
     // a range without pairs still orders its cells behind the predecessors
     wait();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -633,7 +663,9 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_sweep(const DevParams *__rest
         int g = 0;
         while (it >= SW->group_end[g]) ++g;
         // range index within group g
-        fd_flow_range<K, K != 0>(P, SW->launch[g], g, order[it], A, epoch, lds, cnt, negeps);
+        // the batched state loads in place of the constants held in
+        // vector registers: both do not fit in 256 VGPRs
+        fd_flow_range<K, false, 2>(P, SW->launch[g], g, order[it], A, epoch, lds, cnt, negeps);
     }
     fd_flush_counters(cnt, negeps, counters, A.err);
 }
@@ -686,7 +718,7 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_sweep_boxes(const FdBoxDesc *
         const uint32_t gbeg = g > 0 ? D.SW->group_end[g - 1] : 0u;
         FdCount cnt = {0u, 0u, 0u, 0u, 0u};
         bool negeps = false;
-        fd_flow_range<K, false>(*D.Pp, D.SW->launch[g], g, D.order[gbeg + (it - row[lo])], D.A, D.epoch,
+        fd_flow_range<K, false, 0>(*D.Pp, D.SW->launch[g], g, D.order[gbeg + (it - row[lo])], D.A, D.epoch,
                          lds, cnt, negeps);
         fd_flush_counters(cnt, negeps, D.counters, D.A.err);
     }
