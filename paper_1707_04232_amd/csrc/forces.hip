@@ -189,8 +189,7 @@ SDPD_MULTI_KERNEL(k_forces_multi, ForcesArgs, forces_body<1>, 256)
 
 // Boxes above 2^17 particles take one partner loop per layer of neighbour
 // cells; smaller boxes, whose few workgroups leave the pass latency-bound,
-// and the multi-box launches of batches (boxes of at most 64,000 particles)
-// one loop over all 27.
+// and the multi-box launches of batches one loop over all 27.
 constexpr int64_t kLayerMinParticles = (int64_t)1 << 17;
 
 int run_forces(sdpd_ctx *c, const sdpd_state *s, int half_kick)
