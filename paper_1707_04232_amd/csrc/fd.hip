@@ -663,9 +663,9 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_sweep(const DevParams *__rest
         int g = 0;
         while (it >= SW->group_end[g]) ++g;
         // range index within group g
-        // the batched state loads in place of the constants held in
-        // vector registers: both do not fit in 256 VGPRs
-        fd_flow_range<K, false, 2>(P, SW->launch[g], g, order[it], A, epoch, lds, cnt, negeps);
+        // batched state loads; the constants held in vector registers too
+        // where both fit in 256 VGPRs (the FP32-proposal kernel, K = 2)
+        fd_flow_range<K, K == 2, 2>(P, SW->launch[g], g, order[it], A, epoch, lds, cnt, negeps);
     }
     fd_flush_counters(cnt, negeps, counters, A.err);
 }
